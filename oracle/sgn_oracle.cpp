@@ -1,0 +1,613 @@
+// sgn_oracle.cpp -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow CPU evaluation of the energy-conserving split-form SBP
+// semi-discretization of the two-dimensional hyperbolized Serre-Green-Naghdi
+// equations with variable bathymetry (arXiv 2601.02540, Section 4).  It exists
+// so that the tests, the smoke check and the benchmark's CPU-baseline leg can
+// check the HIP path against something written independently from the paper.
+// The product path never links, loads or calls this file.  It shares no code,
+// header, constant or table with paper_2601_02540_amd/csrc.
+//
+// Conventions (all from the paper unless marked "reading"):
+//  * state q = five planes [h, u, v, w, eta], each ny*nx row-major, x fastest;
+//    bathymetry b is one more plane.  Node (i, j) is x_i, y_j.
+//  * 1D operators of Remark "Concrete SBP operators and SATs" (Section 4.2):
+//      periodic:   D = circ(-1, 0, 1)/(2 dx), M = dx I,
+//      reflecting: interior central, first/last rows (-2, 2)/(2 dx),
+//                  M = dx diag(1/2, 1, ..., 1, 1/2), BN = e_R e_R^T - e_L e_L^T.
+//    Reading of the node placement: periodic dx = L/N with the right end point
+//    excluded (so that M = dx I integrates the period exactly); reflecting
+//    dx = L/(N-1) with both end points on the grid.
+//  * 2D operators are tensor products (Section 2.2): D_x acts along i, D_y
+//    along j, M_ij = wx_i * wy_j, and M^{-1} R^T B N_x R = (Mx^{-1} BN_x) (x) I.
+//  * Rates: periodic semi-discretization eq. (sd_periodic_2D_SGN, Section 4.1);
+//    reflecting one eq. (semi_2D, Section 4.2), whose only change is the SAT
+//    pair in the h equation.  The u, v, w rows are printed multiplied by h;
+//    the oracle divides by h.
+//  * Energy E and its gradient d_q E: Theorem 1 proof (Section 4.1).
+//  * Auxiliary initialization eq. (initialization), Section 6.
+//  * Time integration: classical four-stage RK4 with a fixed step (the paper
+//    itself uses an adaptive five-stage FSAL method; see the design notes).
+//
+// Arithmetic is evaluated in the order the equations are printed; build with
+// -O2 -ffp-contract=off so that no fused multiply-add reorders it.
+// Every function is templated on the scalar so that the same source evaluates
+// in double (reference), float (to bound single-precision runs) and
+// std::complex<double> (complex-step directional derivatives for the adjoint
+// and manufactured-solution pins).
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+extern "C" {
+
+typedef struct {
+  int32_t nx, ny;
+  double xmin, xmax, ymin, ymax;
+  int32_t bc_x, bc_y;  // 0 = periodic, 1 = reflecting
+  double g, lambda;
+} orc_grid;
+
+}  // extern "C"
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// One-dimensional SBP operator (Remark "Concrete SBP operators and SATs").
+// D is stored as an explicit list of matrix entries (row, col, value) taken
+// straight from the printed matrices; M and BN are diagonals.
+struct Op1D {
+  int n = 0;
+  int bc = 0;
+  double delta = 0;
+  std::vector<int> row, col;
+  std::vector<double> val;
+  std::vector<double> w;   // diagonal of the mass matrix M
+  std::vector<double> bn;  // diagonal of B N = e_R e_R^T - e_L e_L^T (zero if periodic)
+
+  void add(int r, int c, double v) {
+    row.push_back(r);
+    col.push_back(c);
+    val.push_back(v);
+  }
+};
+
+Op1D make_op(int n, int bc, double lo, double hi) {
+  Op1D op;
+  op.n = n;
+  op.bc = bc;
+  op.w.assign(n, 0.0);
+  op.bn.assign(n, 0.0);
+  if (bc == 0) {
+    op.delta = (hi - lo) / n;
+    const double c = 1.0 / (2.0 * op.delta);
+    for (int i = 0; i < n; ++i) {
+      op.add(i, (i - 1 + n) % n, -c);
+      op.add(i, (i + 1) % n, c);
+      op.w[i] = op.delta;
+    }
+  } else {
+    op.delta = (hi - lo) / (n - 1);
+    const double c = 1.0 / (2.0 * op.delta);
+    op.add(0, 0, -2.0 * c);
+    op.add(0, 1, 2.0 * c);
+    for (int i = 1; i < n - 1; ++i) {
+      op.add(i, i - 1, -c);
+      op.add(i, i + 1, c);
+    }
+    op.add(n - 1, n - 2, -2.0 * c);
+    op.add(n - 1, n - 1, 2.0 * c);
+    for (int i = 0; i < n; ++i) op.w[i] = op.delta;
+    op.w[0] = 0.5 * op.delta;
+    op.w[n - 1] = 0.5 * op.delta;
+    op.bn[0] = -1.0;
+    op.bn[n - 1] = 1.0;
+  }
+  return op;
+}
+
+struct Ops {
+  Op1D x, y;
+  int nx, ny;
+  size_t N;
+};
+
+Ops make_ops(const orc_grid& g) {
+  Ops o;
+  o.x = make_op(g.nx, g.bc_x, g.xmin, g.xmax);
+  o.y = make_op(g.ny, g.bc_y, g.ymin, g.ymax);
+  o.nx = g.nx;
+  o.ny = g.ny;
+  o.N = (size_t)g.nx * (size_t)g.ny;
+  return o;
+}
+
+// out = D_x f : D acting on the x index of every row j.
+template <class T>
+void apply_dx(const Ops& o, const T* f, T* out) {
+  for (size_t k = 0; k < o.N; ++k) out[k] = T(0);
+  for (int j = 0; j < o.ny; ++j)
+    for (size_t e = 0; e < o.x.val.size(); ++e)
+      out[(size_t)j * o.nx + o.x.row[e]] += T(o.x.val[e]) * f[(size_t)j * o.nx + o.x.col[e]];
+}
+
+// out = D_y f : D acting on the y index of every column i.
+template <class T>
+void apply_dy(const Ops& o, const T* f, T* out) {
+  for (size_t k = 0; k < o.N; ++k) out[k] = T(0);
+  for (size_t e = 0; e < o.y.val.size(); ++e)
+    for (int i = 0; i < o.nx; ++i)
+      out[(size_t)o.y.row[e] * o.nx + i] += T(o.y.val[e]) * f[(size_t)o.y.col[e] * o.nx + i];
+}
+
+// out += D_x^T f  (transpose: every entry scatters from its row to its column).
+template <class T>
+void add_dxT(const Ops& o, const T* f, T* out) {
+  for (int j = 0; j < o.ny; ++j)
+    for (size_t e = 0; e < o.x.val.size(); ++e)
+      out[(size_t)j * o.nx + o.x.col[e]] += T(o.x.val[e]) * f[(size_t)j * o.nx + o.x.row[e]];
+}
+
+template <class T>
+void add_dyT(const Ops& o, const T* f, T* out) {
+  for (size_t e = 0; e < o.y.val.size(); ++e)
+    for (int i = 0; i < o.nx; ++i)
+      out[(size_t)o.y.col[e] * o.nx + i] += T(o.y.val[e]) * f[(size_t)o.y.row[e] * o.nx + i];
+}
+
+// Neumaier-compensated sum, row-major order.
+struct Neumaier {
+  double s = 0, c = 0;
+  void add(double x) {
+    double t = s + x;
+    if (std::fabs(s) >= std::fabs(x))
+      c += (s - t) + x;
+    else
+      c += (x - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+// ---------------------------------------------------------------------------
+// Manufactured solution (Section 6.1.2) and its source terms.
+//
+// The fields are the printed b, h, u, v, eta = h, w = -h (u_x + v_y) +
+// 3/2 (u b_x + v b_y).  The sources are the residuals of the continuous system
+// eq. (2D_hyperbolic_SGN) as printed (conservative form), with every partial
+// derivative taken by the complex step, and then converted to the primitive
+// unknowns evolved by the semi-discretization:
+//   S_h = R_h,  S_u = (R_hu - u R_h)/h,  S_v = (R_hv - v R_h)/h,
+//   S_w = (R_hw - w R_h)/h,  S_eta = (R_heta - eta R_h)/h,
+// which follows from (h q)_t = h q_t + q h_t.  The first derivatives u_x, v_y,
+// b_x, b_y inside w are written out from the printed formulas.
+template <class T>
+struct MmsFields {
+  T b, h, u, v, eta, w;
+};
+
+template <class T>
+MmsFields<T> mms_fields(T x, T y, T t) {
+  const double pi = M_PI;
+  const double k = 2.0 * pi;
+  MmsFields<T> f;
+  f.b = 0.08 * (std::cos(k * x) * std::cos(k * y) + 0.5 * std::cos(2.0 * k * x) * std::cos(2.0 * k * y));
+  f.h = 2.0 + 0.5 * std::sin(k * x) * std::sin(k * y) * std::cos(k * t) - f.b;
+  f.u = 0.3 * std::sin(k * x) * std::sin(k * t);
+  f.v = 0.3 * std::sin(k * y) * std::sin(k * t);
+  f.eta = f.h;
+  T ux = 0.3 * k * std::cos(k * x) * std::sin(k * t);
+  T vy = 0.3 * k * std::cos(k * y) * std::sin(k * t);
+  T bx = 0.08 * (-k * std::sin(k * x) * std::cos(k * y) - 0.5 * 2.0 * k * std::sin(2.0 * k * x) * std::cos(2.0 * k * y));
+  T by = 0.08 * (-k * std::cos(k * x) * std::sin(k * y) - 0.5 * 2.0 * k * std::cos(2.0 * k * x) * std::sin(2.0 * k * y));
+  f.w = -f.h * (ux + vy) + 1.5 * (f.u * bx + f.v * by);
+  return f;
+}
+
+const double CS_EPS = 1e-30;
+
+// Conserved quantities and fluxes of eq. (2D_hyperbolic_SGN) built from the
+// fields, with p(h, eta) = lambda/3 (eta/h) (1 - eta/h).
+template <class T>
+struct MmsFluxes {
+  T h, hu, hv, heta, hw;      // conserved variables
+  T fxx, fyy, huv;            // momentum fluxes: h u^2 + g h^2/2 + h p, h v^2 + g h^2/2 + h p, h u v
+  T hetau, hetav, hwu, hwv;   // fluxes of h eta and h w
+  T b;
+};
+
+template <class T>
+MmsFluxes<T> mms_fluxes(const MmsFields<T>& f, double g, double lam) {
+  MmsFluxes<T> F;
+  const T p = lam / 3.0 * (f.eta / f.h) * (1.0 - f.eta / f.h);
+  F.h = f.h;
+  F.hu = f.h * f.u;
+  F.hv = f.h * f.v;
+  F.heta = f.h * f.eta;
+  F.hw = f.h * f.w;
+  F.fxx = f.h * f.u * f.u + 0.5 * g * f.h * f.h + f.h * p;
+  F.fyy = f.h * f.v * f.v + 0.5 * g * f.h * f.h + f.h * p;
+  F.huv = f.h * f.u * f.v;
+  F.hetau = f.h * f.eta * f.u;
+  F.hetav = f.h * f.eta * f.v;
+  F.hwu = f.h * f.w * f.u;
+  F.hwv = f.h * f.w * f.v;
+  F.b = f.b;
+  return F;
+}
+
+// Returns the five primitive sources [S_h, S_u, S_v, S_w, S_eta] at (x, y, t).
+// Each partial derivative of a flux is the imaginary part of that flux built
+// from fields evaluated at a complex-perturbed x, y or t, divided by the step.
+void mms_source_point(double g, double lam, double x, double y, double t, double S[5]) {
+  const MmsFluxes<cplx> Fx = mms_fluxes(mms_fields(cplx(x, CS_EPS), cplx(y, 0), cplx(t, 0)), g, lam);
+  const MmsFluxes<cplx> Fy = mms_fluxes(mms_fields(cplx(x, 0), cplx(y, CS_EPS), cplx(t, 0)), g, lam);
+  const MmsFluxes<cplx> Ft = mms_fluxes(mms_fields(cplx(x, 0), cplx(y, 0), cplx(t, CS_EPS)), g, lam);
+  auto dx = [&](cplx MmsFluxes<cplx>::*m) { return std::imag(Fx.*m) / CS_EPS; };
+  auto dy = [&](cplx MmsFluxes<cplx>::*m) { return std::imag(Fy.*m) / CS_EPS; };
+  auto dt = [&](cplx MmsFluxes<cplx>::*m) { return std::imag(Ft.*m) / CS_EPS; };
+  using F = MmsFluxes<cplx>;
+
+  const MmsFields<double> f = mms_fields<double>(x, y, t);
+  const double bx = dx(&F::b);
+  const double by = dy(&F::b);
+  const double p = lam / 3.0 * (f.eta / f.h) * (1.0 - f.eta / f.h);
+
+  const double Rh = dt(&F::h) + dx(&F::hu) + dy(&F::hv);
+  const double Rhu = dt(&F::hu) + dx(&F::fxx) + dy(&F::huv) + (g * f.h + 1.5 * (f.h / f.eta) * p) * bx;
+  const double Rhv = dt(&F::hv) + dx(&F::huv) + dy(&F::fyy) + (g * f.h + 1.5 * (f.h / f.eta) * p) * by;
+  const double Rheta = dt(&F::heta) + dx(&F::hetau) + dy(&F::hetav) + 1.5 * f.h * (f.u * bx + f.v * by) - f.h * f.w;
+  const double Rhw = dt(&F::hw) + dx(&F::hwu) + dy(&F::hwv) - lam * (1.0 - f.eta / f.h);
+
+  S[0] = Rh;
+  S[1] = (Rhu - f.u * Rh) / f.h;
+  S[2] = (Rhv - f.v * Rh) / f.h;
+  S[3] = (Rhw - f.w * Rh) / f.h;
+  S[4] = (Rheta - f.eta * Rh) / f.h;
+}
+
+double node_x(const Ops& o, const orc_grid& g, int i) { return g.xmin + i * o.x.delta; }
+double node_y(const Ops& o, const orc_grid& g, int j) { return g.ymin + j * o.y.delta; }
+
+// ---------------------------------------------------------------------------
+// Right-hand side of the semi-discretization.
+template <class T>
+void rhs_impl(const orc_grid& gr, const Ops& o, const T* q, const T* b, double t, int src, T* dq) {
+  const size_t N = o.N;
+  const T* h = q;
+  const T* u = q + N;
+  const T* v = q + 2 * N;
+  const T* w = q + 3 * N;
+  const T* eta = q + 4 * N;
+  const T g = T(gr.g);
+  const T lam = T(gr.lambda);
+  const T half = T(0.5);
+
+  // Pointwise (componentwise) products.
+  std::vector<T> H(N), hH(N), u2(N), v2(N), hu(N), hv(N), huv(N), uv(N), e2h(N), huw(N), hvw(N), uw(N), vw(N), hw(N);
+  for (size_t k = 0; k < N; ++k) {
+    H[k] = h[k] + b[k];
+    hH[k] = h[k] * H[k];
+    u2[k] = u[k] * u[k];
+    v2[k] = v[k] * v[k];
+    hu[k] = h[k] * u[k];
+    hv[k] = h[k] * v[k];
+    huv[k] = h[k] * u[k] * v[k];
+    uv[k] = u[k] * v[k];
+    e2h[k] = eta[k] * eta[k] / h[k];
+    huw[k] = h[k] * u[k] * w[k];
+    hvw[k] = h[k] * v[k] * w[k];
+    uw[k] = u[k] * w[k];
+    vw[k] = v[k] * w[k];
+    hw[k] = h[k] * w[k];
+  }
+
+  // First derivatives.
+  std::vector<T> Dxh(N), Dxu(N), Dxv(N), Dxw(N), Dxeta(N), Dxb(N), DxhH(N), Dxu2(N), Dxhu(N), Dxhuv(N), Dxe2h(N), Dxhuw(N);
+  std::vector<T> Dyh(N), Dyu(N), Dyv(N), Dyw(N), Dyeta(N), Dyb(N), DyhH(N), Dyv2(N), Dyhv(N), Dyhuv(N), Dye2h(N), Dyhvw(N);
+  apply_dx(o, h, Dxh.data());
+  apply_dx(o, u, Dxu.data());
+  apply_dx(o, v, Dxv.data());
+  apply_dx(o, w, Dxw.data());
+  apply_dx(o, eta, Dxeta.data());
+  apply_dx(o, b, Dxb.data());
+  apply_dx(o, hH.data(), DxhH.data());
+  apply_dx(o, u2.data(), Dxu2.data());
+  apply_dx(o, hu.data(), Dxhu.data());
+  apply_dx(o, huv.data(), Dxhuv.data());
+  apply_dx(o, e2h.data(), Dxe2h.data());
+  apply_dx(o, huw.data(), Dxhuw.data());
+  apply_dy(o, h, Dyh.data());
+  apply_dy(o, u, Dyu.data());
+  apply_dy(o, v, Dyv.data());
+  apply_dy(o, w, Dyw.data());
+  apply_dy(o, eta, Dyeta.data());
+  apply_dy(o, b, Dyb.data());
+  apply_dy(o, hH.data(), DyhH.data());
+  apply_dy(o, v2.data(), Dyv2.data());
+  apply_dy(o, hv.data(), Dyhv.data());
+  apply_dy(o, huv.data(), Dyhuv.data());
+  apply_dy(o, e2h.data(), Dye2h.data());
+  apply_dy(o, hvw.data(), Dyhvw.data());
+
+  for (int j = 0; j < o.ny; ++j) {
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      // SATs, eq. (semi_2D): M^{-1} R^T B N_x R (h u) and the same in y.
+      T satx = T(0), saty = T(0);
+      if (gr.bc_x == 1) satx = T(o.x.bn[i] / o.x.w[i]) * hu[k];
+      if (gr.bc_y == 1) saty = T(o.y.bn[j] / o.y.w[j]) * hv[k];
+
+      // h equation
+      const T ht = -(u[k] * Dxh[k] + h[k] * Dxu[k] + v[k] * Dyh[k] + h[k] * Dyv[k]) + satx + saty;
+
+      // h u_t + A = 0
+      const T r = eta[k] / h[k];
+      const T r2 = (eta[k] * eta[k]) / (h[k] * h[k]);
+      const T A = g * DxhH[k] - g * H[k] * Dxh[k] + half * h[k] * Dxu2[k] - half * u2[k] * Dxh[k] +
+                  half * u[k] * Dxhu[k] - half * hu[k] * Dxu[k] + half * Dyhuv[k] - half * uv[k] * Dyh[k] +
+                  half * hv[k] * Dyu[k] - half * hu[k] * Dyv[k] + lam / T(6) * r2 * Dxh[k] + lam / T(3) * Dxeta[k] -
+                  lam / T(3) * r * Dxeta[k] - lam / T(6) * Dxe2h[k] + lam / T(2) * (T(1) - r) * Dxb[k];
+      // h v_t + B = 0
+      const T B = g * DyhH[k] - g * H[k] * Dyh[k] + half * h[k] * Dyv2[k] - half * v2[k] * Dyh[k] +
+                  half * v[k] * Dyhv[k] - half * hv[k] * Dyv[k] + half * Dxhuv[k] - half * uv[k] * Dxh[k] +
+                  half * hu[k] * Dxv[k] - half * hv[k] * Dxu[k] + lam / T(6) * r2 * Dyh[k] + lam / T(3) * Dyeta[k] -
+                  lam / T(3) * r * Dyeta[k] - lam / T(6) * Dye2h[k] + lam / T(2) * (T(1) - r) * Dyb[k];
+      // h w_t + C = lambda (1 - eta/h)
+      const T C = half * Dxhuw[k] + half * hu[k] * Dxw[k] - half * uw[k] * Dxh[k] - half * hw[k] * Dxu[k] +
+                  half * Dyhvw[k] + half * hv[k] * Dyw[k] - half * vw[k] * Dyh[k] - half * hw[k] * Dyv[k];
+      // eta_t + (...) = w
+      const T et = w[k] - (u[k] * Dxeta[k] + v[k] * Dyeta[k] + T(1.5) * u[k] * Dxb[k] + T(1.5) * v[k] * Dyb[k]);
+
+      dq[k] = ht;
+      dq[N + k] = -A / h[k];
+      dq[2 * N + k] = -B / h[k];
+      dq[3 * N + k] = (lam * (T(1) - r) - C) / h[k];
+      dq[4 * N + k] = et;
+    }
+  }
+
+  if (src == 1) {
+    for (int j = 0; j < o.ny; ++j)
+      for (int i = 0; i < o.nx; ++i) {
+        double S[5];
+        mms_source_point(gr.g, gr.lambda, node_x(o, gr, i), node_y(o, gr, j), t, S);
+        const size_t k = (size_t)j * o.nx + i;
+        for (int f = 0; f < 5; ++f) dq[f * N + k] += T(S[f]);
+      }
+  }
+}
+
+// Classical RK4 with a fixed step, one step.
+template <class T>
+void rk4_step_impl(const orc_grid& gr, const Ops& o, T* q, const T* b, double dt, double t, int src) {
+  const size_t M = 5 * o.N;
+  std::vector<T> k1(M), k2(M), k3(M), k4(M), Y(M);
+  const T Tdt = T(dt);
+  rhs_impl(gr, o, q, b, t, src, k1.data());
+  for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt / T(2) * k1[k];
+  rhs_impl(gr, o, Y.data(), b, t + dt / 2, src, k2.data());
+  for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt / T(2) * k2[k];
+  rhs_impl(gr, o, Y.data(), b, t + dt / 2, src, k3.data());
+  for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt * k3[k];
+  rhs_impl(gr, o, Y.data(), b, t + dt, src, k4.data());
+  for (size_t k = 0; k < M; ++k) q[k] = q[k] + Tdt * (k1[k] + T(2) * k2[k] + T(2) * k3[k] + k4[k]) / T(6);
+}
+
+// Energy density E = h ((u^2+v^2)/2 + e), e = w^2/6 + g/2 (h + 2b) + lambda/6 (eta/h - 1)^2.
+double energy_density(double g, double lam, double h, double u, double v, double w, double eta, double b) {
+  const double e = w * w / 6.0 + g / 2.0 * (h + 2.0 * b) + lam / 6.0 * (eta / h - 1.0) * (eta / h - 1.0);
+  return h * ((u * u + v * v) / 2.0 + e);
+}
+
+template <class T>
+void init_aux_impl(const Ops& o, T* q, const T* b) {
+  const size_t N = o.N;
+  T* h = q;
+  T* u = q + N;
+  T* v = q + 2 * N;
+  T* w = q + 3 * N;
+  T* eta = q + 4 * N;
+  std::vector<T> Dxu(N), Dyv(N), Dxb(N), Dyb(N);
+  apply_dx(o, u, Dxu.data());
+  apply_dy(o, v, Dyv.data());
+  apply_dx(o, b, Dxb.data());
+  apply_dy(o, b, Dyb.data());
+  for (size_t k = 0; k < N; ++k) {
+    eta[k] = h[k];
+    w[k] = -h[k] * (Dxu[k] + Dyv[k]) + T(1.5) * (u[k] * Dxb[k] + v[k] * Dyb[k]);
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C entry points used by the Python test harness (ctypes).  All pointers are
+// host pointers; q is 5*nx*ny values, b is nx*ny values.
+extern "C" {
+
+// Grid spacing along each axis (reading of the node placement above).
+void orc_spacing(const orc_grid* g, double* dx, double* dy) {
+  Ops o = make_ops(*g);
+  *dx = o.x.delta;
+  *dy = o.y.delta;
+}
+
+// The 1D operator as a dense n x n matrix (row-major), its mass diagonal and
+// the diagonal of B N.
+void orc_op1d_dense(int n, int bc, double lo, double hi, double* D, double* w, double* bn) {
+  Op1D op = make_op(n, bc, lo, hi);
+  for (int k = 0; k < n * n; ++k) D[k] = 0.0;
+  for (size_t e = 0; e < op.val.size(); ++e) D[(size_t)op.row[e] * n + op.col[e]] += op.val[e];
+  for (int i = 0; i < n; ++i) {
+    w[i] = op.w[i];
+    bn[i] = op.bn[i];
+  }
+}
+
+void orc_apply_dx(const orc_grid* g, const double* f, double* out) {
+  Ops o = make_ops(*g);
+  apply_dx(o, f, out);
+}
+void orc_apply_dy(const orc_grid* g, const double* f, double* out) {
+  Ops o = make_ops(*g);
+  apply_dy(o, f, out);
+}
+
+void orc_rhs(const orc_grid* g, const double* q, const double* b, double t, int src, double* dq) {
+  Ops o = make_ops(*g);
+  rhs_impl<double>(*g, o, q, b, t, src, dq);
+}
+
+void orc_rhs_f32(const orc_grid* g, const float* q, const float* b, double t, int src, float* dq) {
+  Ops o = make_ops(*g);
+  rhs_impl<float>(*g, o, q, b, t, src, dq);
+}
+
+// Directional derivative of the right-hand side by the complex step:
+// out = d/de rhs(q + e dq_dir, b + e db_dir) at e = 0, exact to rounding.
+void orc_rhs_jvp(const orc_grid* g, const double* q, const double* b, const double* dq_dir, const double* db_dir,
+                 double* out) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  std::vector<cplx> qc(5 * N), bc(N), dqc(5 * N);
+  for (size_t k = 0; k < 5 * N; ++k) qc[k] = cplx(q[k], CS_EPS * dq_dir[k]);
+  for (size_t k = 0; k < N; ++k) bc[k] = cplx(b[k], db_dir ? CS_EPS * db_dir[k] : 0.0);
+  rhs_impl<cplx>(*g, o, qc.data(), bc.data(), 0.0, 0, dqc.data());
+  for (size_t k = 0; k < 5 * N; ++k) out[k] = std::imag(dqc[k]) / CS_EPS;
+}
+
+void orc_rk4(const orc_grid* g, double* q, const double* b, double dt, double t0, int64_t nsteps, int src) {
+  Ops o = make_ops(*g);
+  for (int64_t s = 0; s < nsteps; ++s) rk4_step_impl<double>(*g, o, q, b, dt, t0 + s * dt, src);
+}
+
+void orc_rk4_f32(const orc_grid* g, float* q, const float* b, double dt, double t0, int64_t nsteps, int src) {
+  Ops o = make_ops(*g);
+  for (int64_t s = 0; s < nsteps; ++s) rk4_step_impl<float>(*g, o, q, b, dt, t0 + s * dt, src);
+}
+
+void orc_init_aux(const orc_grid* g, double* q, const double* b) {
+  Ops o = make_ops(*g);
+  init_aux_impl<double>(o, q, b);
+}
+
+// Total mass 1^T M h and total energy 1^T M E (Theorems 1 and 2).
+void orc_mass_energy(const orc_grid* g, const double* q, const double* b, double* mass, double* energy) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  Neumaier sm, se;
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      const double Mk = o.x.w[i] * o.y.w[j];
+      sm.add(Mk * q[k]);
+      se.add(Mk * energy_density(g->g, g->lambda, q[k], q[N + k], q[2 * N + k], q[3 * N + k], q[4 * N + k], b[k]));
+    }
+  *mass = sm.value();
+  *energy = se.value();
+}
+
+// Same totals for a single-precision state, accumulated in double.
+void orc_mass_energy_f32(const orc_grid* g, const float* q, const float* b, double* mass, double* energy) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  Neumaier sm, se;
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      const double Mk = o.x.w[i] * o.y.w[j];
+      sm.add(Mk * (double)q[k]);
+      se.add(Mk * energy_density(g->g, g->lambda, q[k], q[N + k], q[2 * N + k], q[3 * N + k], q[4 * N + k], b[k]));
+    }
+  *mass = sm.value();
+  *energy = se.value();
+}
+
+// Semi-discrete rates: mass_rate = 1^T M h_t, energy_rate = <d_q E, q_t>_M with
+// d_h E = u^2/2 + v^2/2 + w^2/6 + g h + g b + lambda/6 (1 - eta^2/h^2),
+// d_u E = h u, d_v E = h v, d_w E = h w / 3, d_eta E = -lambda/3 (1 - eta/h).
+// scale[0] = sum M |h_t|, scale[1] = sum M (|d_h E h_t| + ... + |d_eta E eta_t|).
+void orc_rates(const orc_grid* g, const double* q, const double* b, double* mass_rate, double* energy_rate,
+               double* scale) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  std::vector<double> dq(5 * N);
+  rhs_impl<double>(*g, o, q, b, 0.0, 0, dq.data());
+  Neumaier sm, se, am, ae;
+  const double G = g->g, lam = g->lambda;
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      const double Mk = o.x.w[i] * o.y.w[j];
+      const double h = q[k], u = q[N + k], v = q[2 * N + k], w = q[3 * N + k], eta = q[4 * N + k];
+      const double dEh = 0.5 * u * u + 0.5 * v * v + w * w / 6.0 + G * h + G * b[k] +
+                         lam / 6.0 * (1.0 - (eta * eta) / (h * h));
+      const double dEu = h * u, dEv = h * v, dEw = h * w / 3.0, dEeta = -lam / 3.0 * (1.0 - eta / h);
+      const double t1 = dEh * dq[k], t2 = dEu * dq[N + k], t3 = dEv * dq[2 * N + k], t4 = dEw * dq[3 * N + k],
+                   t5 = dEeta * dq[4 * N + k];
+      sm.add(Mk * dq[k]);
+      se.add(Mk * t1);
+      se.add(Mk * t2);
+      se.add(Mk * t3);
+      se.add(Mk * t4);
+      se.add(Mk * t5);
+      am.add(Mk * std::fabs(dq[k]));
+      ae.add(Mk * (std::fabs(t1) + std::fabs(t2) + std::fabs(t3) + std::fabs(t4) + std::fabs(t5)));
+    }
+  *mass_rate = sm.value();
+  *energy_rate = se.value();
+  scale[0] = am.value();
+  scale[1] = ae.value();
+}
+
+// Time step from the characteristic speeds of the hyperbolic system (reading:
+// c^2 = g h + lambda eta^2 / (3 h^2) from the x-flux Jacobian in primitive
+// variables), dt = cfl / max_ij [(|u|+c)/dx + (|v|+c)/dy].
+double orc_cfl_dt(const orc_grid* g, const double* q, double cfl) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  double m = 0.0;
+  for (size_t k = 0; k < N; ++k) {
+    const double h = q[k], u = q[N + k], v = q[2 * N + k], eta = q[4 * N + k];
+    const double c = std::sqrt(g->g * h + g->lambda * eta * eta / (3.0 * h * h));
+    const double s = (std::fabs(u) + c) / o.x.delta + (std::fabs(v) + c) / o.y.delta;
+    if (s > m) m = s;
+  }
+  return cfl / m;
+}
+
+// Manufactured solution sampled on the grid at time t: q (5 planes) and b.
+void orc_mms_fields(const orc_grid* g, double t, double* q, double* b) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      MmsFields<double> f = mms_fields<double>(node_x(o, *g, i), node_y(o, *g, j), t);
+      q[k] = f.h;
+      q[N + k] = f.u;
+      q[2 * N + k] = f.v;
+      q[3 * N + k] = f.w;
+      q[4 * N + k] = f.eta;
+      b[k] = f.b;
+    }
+}
+
+void orc_mms_source(const orc_grid* g, double t, double* S) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      double s[5];
+      mms_source_point(g->g, g->lambda, node_x(o, *g, i), node_y(o, *g, j), t, s);
+      for (int f = 0; f < 5; ++f) S[f * N + (size_t)j * o.nx + i] = s[f];
+    }
+}
+
+}  // extern "C"
