@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the fused split-form SBP + RK4 step on one MI355X.
+
+Default workload: the large single run -- periodic [-50,50]^2 on a 4096 x 4096
+grid, random-phase bathymetry (amplitude 0.2) under a still-water level of 1,
+a seeded Gaussian surface bump, lambda = 500, g = 9.81, classical RK4 with a
+fixed step at CFL 0.5, FP64 state and arithmetic.  A "step" is one RK4 step
+(four fused stage kernels) over the whole grid; the value is RK-stage
+cell-updates per second, nx * ny * 4 * steps / seconds, with all inputs
+resident in HBM before the timed region starts.
+
+The same run is repeated with reflecting walls and with FP32 storage and
+arithmetic (energy and mass still reduced in FP64), reported under
+"variants".  The CPU oracle times one RK4 step of the same workload on the
+host as a baseline.
+
+Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RK-stage cell-updates/s and % HBM peak (FP64 vs FP32); adjoint:forward cost"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic traffic of one fused RK4 step in three-register form, in values
+# per cell: stage 1 reads q, b and writes acc, Y (16); stages 2 and 3 read Y, b,
+# q, acc and write acc, Y (26 each); stage 4 reads Y, b, acc and writes q (16).
+VALUES_PER_STEP = 84
+VALUES_PER_STAGE = VALUES_PER_STEP / 4.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def lake_at_rest_energy(grid, b, mass):
+    """Energy of the lake at rest holding the same mass: g/2 sum M (H^2 - b^2),
+    H = (mass + sum M b) / sum M (the datum of the potential energy is b)."""
+    import numpy as np
+    wx = np.full(grid.nx, grid.spacing()[0])
+    wy = np.full(grid.ny, grid.spacing()[1])
+    if grid.bc_x == 1:
+        wx[0] *= 0.5
+        wx[-1] *= 0.5
+    if grid.bc_y == 1:
+        wy[0] *= 0.5
+        wy[-1] *= 0.5
+    M = np.outer(wy, wx)
+    H = (mass + (M * b).sum()) / M.sum()
+    return 0.5 * grid.g * (M * (H * H - b * b)).sum()
+
+
+def run_gpu(problem, dtype, steps, warmup, label):
+    import numpy as np
+    import torch
+    from paper_2601_02540_amd.binding import Solver
+
+    grid = problem.grid
+    s = Solver(grid, dtype)
+    b = torch.from_numpy(problem.b).to(dtype).cuda().contiguous()
+    q = torch.from_numpy(problem.q0).to(dtype).cuda().contiguous()
+    s.set_bathymetry(b)
+    s.init_aux(q)
+    dt = s.cfl_dt(q, 0.5)
+    m0, e0 = s.mass_energy(q)
+    log(f"[{label}] dt={dt:.6e} warmup={warmup}")
+    if warmup > 0:
+        s.step(q, dt, warmup)
+    torch.cuda.synchronize()
+    stream = s.stream
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    t_start.record(stream)
+    s.step(q, dt, steps, t0=warmup * dt)
+    t_end.record(stream)
+    t_end.synchronize()
+    torch.cuda.synchronize()
+    sec = t_start.elapsed_time(t_end) / 1e3
+    s.check()
+    m1, e1 = s.mass_energy(q)
+    cells = grid.nx * grid.ny
+    esize = 8 if dtype == torch.float64 else 4
+    launch_s = sec / (4 * steps)
+    achieved = VALUES_PER_STAGE * esize * cells / launch_s / 1e9
+    # per-mode durations of the four stage kernels (direct launches with HIP events)
+    ms = s.profile_stages(q, dt, 5)
+    e_rest = lake_at_rest_energy(grid, problem.b.astype(np.float64), m0)
+    res = {
+        "value": cells * 4 * steps / sec,
+        "sec": sec,
+        "ms_per_step": sec / steps * 1e3,
+        "dt": dt,
+        "stage_launch_us": launch_s * 1e6,
+        "achieved_GBs": achieved,
+        "frac": achieved / HBM_PEAK_GBS,
+        "stage_ms_by_mode": {"first": ms[0], "mid1": ms[1], "mid2": ms[2], "last": ms[3]},
+        "mass_drift_rel": (m1 - m0) / abs(m0),
+        "energy_drift_rel": (e1 - e0) / abs(e0),
+        "energy_drift_rel_to_excess": (e1 - e0) / abs(e0 - e_rest),
+        "energy_final": e1,
+    }
+    log(f"[{label}] {res['value']:.4e} cell-stage/s  {res['ms_per_step']:.3f} ms/step  "
+        f"{achieved:.0f} GB/s ({100 * res['frac']:.1f}% of HBM peak)  dE/E={res['energy_drift_rel']:.3e}")
+    s.close()
+    del q, b
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(problem, steps=1):
+    """The FP64 oracle (single thread, as written) on the same workload."""
+    import numpy as np
+    import oracle
+    oracle.build() if not os.path.exists(oracle._LIB) else None
+    q = oracle.init_aux(problem.grid, problem.q0, problem.b)
+    dt = oracle.cfl_dt(problem.grid, q, 0.5)
+    t0 = time.perf_counter()
+    oracle.rk4(problem.grid, q, problem.b, dt, steps)
+    sec = time.perf_counter() - t0
+    cells = problem.grid.nx * problem.grid.ny
+    return {"value": cells * 4 * steps / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 step(s) of the same {problem.grid.nx}x{problem.grid.ny} FP64 workload "
+                      f"({sec:.1f} s, single-threaded C++ -O2 -ffp-contract=off)"}
+
+
+def calib_copy(nbytes):
+    """A plain device copy of known size, for scaling rocprof FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[calib] copied {nbytes} bytes x3")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=4096, help="grid nodes per axis")
+    ap.add_argument("--no-variants", action="store_true", help="skip the reflecting and FP32 repeats")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1",
+                          "requested_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_02540_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no ROCm GPU visible"}), flush=True)
+        sys.exit(1)
+
+    if args.calib_copy:
+        calib_copy(args.calib_copy)
+
+    n = args.n
+    log(f"[bench] generating {n}x{n} workload")
+    prob = W.random_phase_large(n, W.PERIODIC, seed=3)
+    main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64")
+
+    variants = {}
+    if not args.no_variants:
+        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32")
+        variants["periodic_f32"]["energy_diff_vs_f64_rel"] = (
+            (variants["periodic_f32"]["energy_final"] - main_res["energy_final"]) / abs(main_res["energy_final"]))
+        probr = W.random_phase_large(n, W.REFLECTING, seed=3)
+        variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64")
+        variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on one step of the same workload")
+        cpu = cpu_baseline(prob, 1)
+        log(f"[bench] cpu {cpu['value']:.3e} cell-stage/s")
+
+    cells = n * n
+    line = {
+        "metric": METRIC,
+        "value": main_res["value"],
+        "unit": "cell-stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"random-phase bathymetry, Gaussian bump, periodic [-50,50]^2, {n}x{n}, "
+                               f"lambda=500, RK4 fixed dt (CFL 0.5)",
+                   "nx": n, "ny": n, "cells": cells, "bc": "periodic", "lambda": 500.0, "g": 9.81,
+                   "dt": main_res["dt"], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": main_res["frac"], "traffic": None,
+                     "kernel": "stage_kernel (fused RHS + RK4 stage; mean over the 4 stage launches of a step)",
+                     "algorithmic_bytes_per_cell_stage": VALUES_PER_STAGE * 8},
+        "cpu_baseline": cpu,
+        "energy_drift_rel": main_res["energy_drift_rel"],
+        "energy_drift_rel_to_excess": main_res["energy_drift_rel_to_excess"],
+        "mass_drift_rel": main_res["mass_drift_rel"],
+        "stage_ms_by_mode": main_res["stage_ms_by_mode"],
+        "variants": {k: {kk: vv for kk, vv in v.items() if kk not in ("energy_final",)} for k, v in variants.items()},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * sgn.h -- C ABI of the MI355X (gfx950) solver for the energy-conserving
+ * split-form SBP semi-discretization of the two-dimensional hyperbolized
+ * Serre-Green-Naghdi equations with variable bathymetry (arXiv 2601.02540).
+ *
+ * Problem statement followed by the calls (paper references):
+ *   unknowns h, u, v, w, eta and static bathymetry b, gravity g, relaxation
+ *   parameter lambda: eq. (2D_hyperbolic_SGN), Section 3.2;
+ *   nodal grid and SBP operators (D, M): Section 2.2 and Remark "Concrete SBP
+ *   operators and SATs" (second-order central differences; periodic, or
+ *   first-order one-sided closures with a trapezoid mass matrix);
+ *   right-hand side: eq. (sd_periodic_2D_SGN) (periodic) and eq. (semi_2D)
+ *   (reflecting walls, weak SATs in the h equation only);
+ *   total mass 1^T M h and energy 1^T M E: Theorems 1 and 2;
+ *   auxiliary initialization: eq. (initialization), Section 6.
+ *
+ * Memory layout.  A state q is five contiguous planes [h, u, v, w, eta], each
+ * ny*nx values, row-major with x (index i) fastest: q[f*nx*ny + j*nx + i].
+ * The bathymetry is one such plane.  All array arguments are DEVICE pointers
+ * on the context's device, in the context's storage type (double for
+ * SGN_F64, float for SGN_F32), unless documented otherwise.  Scalars returned
+ * to the caller (mass, energy, rates, dt) are host doubles.
+ *
+ * Node placement: a periodic axis [lo, hi) has N nodes spaced (hi-lo)/N (the
+ * right end point is the image of the left one); a reflecting axis [lo, hi]
+ * has N nodes spaced (hi-lo)/(N-1) including both walls.
+ *
+ * Ownership.  The caller owns every array it passes.  The context owns a copy
+ * of b, the Runge-Kutta scratch planes, reduction partials, captured graphs
+ * and a device health flag.  Nothing is retained past a call except the copy
+ * of b and the stream.
+ *
+ * Asynchrony.  Calls that return no host value (set_bathymetry, init_aux, rhs,
+ * step) only enqueue work on the context's stream and return.  Calls that
+ * return host values (mass, energy, mass_energy, rates, cfl_dt, check)
+ * synchronize the stream.  Launch failures are reported immediately.
+ *
+ * Errors.  Every call returns an sgn_status; no exception crosses the ABI.
+ * A call that fails leaves a message for sgn_last_error().  Kernels raise a
+ * device flag when a step produces h <= 0 or a non-finite value (the method
+ * has no wetting and drying); the flag is reported as SGN_E_NONPOS_DEPTH or
+ * SGN_E_NONFINITE by the next synchronizing call and then cleared.
+ *
+ * Threading.  One context belongs to one stream; calls on the same context
+ * must not overlap.  Different contexts are independent.
+ */
+#ifndef SGN_H
+#define SGN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SGN_OK = 0,
+  SGN_E_ARG = -1,           /* null pointer, non-finite or negative parameter */
+  SGN_E_SHAPE = -2,         /* fewer than 4 nodes on an axis, empty domain, overflow */
+  SGN_E_UNSUPPORTED = -3,   /* option not available for this dtype/boundary combination */
+  SGN_E_HIP = -4,           /* HIP runtime error (message has the HIP error string) */
+  SGN_E_NONPOS_DEPTH = -5,  /* a kernel saw h <= 0 */
+  SGN_E_NONFINITE = -6,     /* a kernel saw NaN or Inf in the state */
+  SGN_E_ALLOC = -7,         /* device allocation failed */
+  SGN_E_STATE = -8          /* call out of order (e.g. bathymetry never set) */
+} sgn_status;
+
+typedef enum { SGN_PERIODIC = 0, SGN_REFLECTING = 1 } sgn_bc;
+typedef enum { SGN_F64 = 0, SGN_F32 = 1 } sgn_dtype;
+
+/* Source terms added to the right-hand side at stage time.
+ * SGN_SRC_MMS: the manufactured solution of Section 6.1.2 (domain [-1,1]^2):
+ * the analytic residual of eq. (2D_hyperbolic_SGN) in the evolved
+ * (primitive) variables is added to every stage, evaluated at t_n + c_s dt. */
+typedef enum { SGN_SRC_NONE = 0, SGN_SRC_MMS = 1 } sgn_source;
+
+typedef struct {
+  int32_t nx, ny;           /* nodes per axis, each >= 4 */
+  double xmin, xmax;        /* domain along x (xmax > xmin) */
+  double ymin, ymax;        /* domain along y (ymax > ymin) */
+  int32_t bc_x, bc_y;       /* sgn_bc per axis (the two may differ) */
+  double g;                 /* gravitational acceleration, > 0 */
+  double lambda;            /* hyperbolization (relaxation) parameter, >= 0 */
+  int32_t dtype;            /* sgn_dtype: storage and arithmetic of the state */
+  int32_t source;           /* sgn_source */
+} sgn_params;
+
+typedef struct sgn_ctx sgn_ctx;
+
+/* Create a context on the current HIP device.  stream is a hipStream_t (NULL
+ * for the null stream).  Allocates the Runge-Kutta scratch (three states), a
+ * bathymetry plane and the reduction partials.  On failure *out is NULL. */
+sgn_status sgn_create(const sgn_params* params, void* stream, sgn_ctx** out);
+
+/* Free everything the context owns (synchronizes its stream first). NULL is a no-op. */
+sgn_status sgn_destroy(sgn_ctx* ctx);
+
+/* Change the stream later calls are enqueued on (invalidates captured graphs). */
+sgn_status sgn_set_stream(sgn_ctx* ctx, void* stream);
+
+/* Copy the bathymetry b (device, one plane) into the context.  Required before
+ * any call that evaluates the right-hand side or the energy. */
+sgn_status sgn_set_bathymetry(sgn_ctx* ctx, const void* b);
+
+/* In place on q: eta = h and w = -h (D_x u + D_y v) + 3/2 (u D_x b + v D_y b)
+ * with the discrete operators (eq. (initialization)).  h, u, v are read. */
+sgn_status sgn_init_aux(sgn_ctx* ctx, void* q);
+
+/* dq = right-hand side of the semi-discretization at state q and time t (t
+ * only matters with a source).  q and dq must not overlap. */
+sgn_status sgn_rhs(sgn_ctx* ctx, const void* q, void* dq, double t);
+
+/* Advance q in place by nsteps steps of the classical four-stage Runge-Kutta
+ * method with fixed step dt, starting at time t0.  Each stage is one fused
+ * kernel (right-hand side plus the stage update).  nsteps == 0 is a no-op.
+ * Without a source the steps are replayed from a captured HIP graph. */
+sgn_status sgn_step(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0);
+
+/* Total mass 1^T M h (FP64 result, compensated deterministic summation). */
+sgn_status sgn_mass(sgn_ctx* ctx, const void* q, double* out);
+
+/* Total energy 1^T M E with E = h((u^2+v^2)/2 + w^2/6 + g/2 (h+2b)
+ * + lambda/6 (eta/h - 1)^2) (FP64 result). */
+sgn_status sgn_energy(sgn_ctx* ctx, const void* q, double* out);
+
+/* Both totals in one pass. */
+sgn_status sgn_mass_energy(sgn_ctx* ctx, const void* q, double* mass, double* energy);
+
+/* Semi-discrete rates 1^T M h_t and <d_q E, q_t>_M (Theorem 1 proof); both
+ * vanish up to rounding for any state with h > 0.  Uses the context's scratch. */
+sgn_status sgn_rates(sgn_ctx* ctx, const void* q, double* mass_rate, double* energy_rate);
+
+/* dt = cfl / max_ij [(|u|+c)/dx + (|v|+c)/dy] with c^2 = g h + lambda eta^2/(3 h^2). */
+sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
+
+/* Measurement: advance q by nsteps RK4 steps exactly like sgn_step but with
+ * direct launches, recording HIP events on the context's stream around each of
+ * the four stage kernels.  ms[s] receives the mean duration of stage s
+ * (0 = first, 1 and 2 = middle, 3 = last) in milliseconds.  Synchronizes. */
+sgn_status sgn_profile_stages(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* ms);
+
+/* Synchronize and report (then clear) the device health flag. */
+sgn_status sgn_check(sgn_ctx* ctx);
+
+/* Grid spacing used by the context (host doubles). */
+sgn_status sgn_spacing(const sgn_ctx* ctx, double* dx, double* dy);
+
+/* Message of the last failed call on ctx (or of the last failed sgn_create when ctx is NULL). */
+const char* sgn_last_error(const sgn_ctx* ctx);
+
+/* Static name of a status code. */
+const char* sgn_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGN_H */

@@ -1,0 +1,217 @@
+"""Thin ctypes binding of the C ABI in ``include/sgn.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library ``libsgn.so``.  PyTorch supplies device memory (tensors) and the stream
+(the current stream when a :class:`Solver` is created).  There is no CPU
+fallback: without a GPU or without the built library every entry point raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import List, Optional, Tuple
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libsgn.so")
+HEADER_PATH = os.path.join(ROOT, "include", "sgn.h")
+
+SGN_F64, SGN_F32 = 0, 1
+SGN_SRC_NONE, SGN_SRC_MMS = 0, 1
+
+
+class SgnError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_name(status)} ({status}): {message}")
+        self.status = status
+
+
+class SgnParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("xmin", ctypes.c_double), ("xmax", ctypes.c_double),
+                ("ymin", ctypes.c_double), ("ymax", ctypes.c_double),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("g", ctypes.c_double), ("lam", ctypes.c_double),
+                ("dtype", ctypes.c_int32), ("source", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def header_symbols() -> List[str]:
+    """Every function declared in include/sgn.h."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(sgn_[a-z0-9_]+)\s*\(", text, re.M)))
+
+
+def load_library() -> ctypes.CDLL:
+    """Loads libsgn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2601_02540_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, cvp = ctypes.c_void_p, ctypes.c_void_p
+    d, dp = ctypes.c_double, ctypes.POINTER(ctypes.c_double)
+    st = ctypes.c_int32
+    sigs = {
+        "sgn_create": ([ctypes.POINTER(SgnParams), vp, ctypes.POINTER(vp)], st),
+        "sgn_destroy": ([vp], st),
+        "sgn_set_stream": ([vp, vp], st),
+        "sgn_set_bathymetry": ([vp, cvp], st),
+        "sgn_init_aux": ([vp, vp], st),
+        "sgn_rhs": ([vp, cvp, vp, d], st),
+        "sgn_step": ([vp, vp, d, ctypes.c_int64, d], st),
+        "sgn_mass": ([vp, cvp, dp], st),
+        "sgn_energy": ([vp, cvp, dp], st),
+        "sgn_mass_energy": ([vp, cvp, dp, dp], st),
+        "sgn_rates": ([vp, cvp, dp, dp], st),
+        "sgn_cfl_dt": ([vp, cvp, d, dp], st),
+        "sgn_check": ([vp], st),
+        "sgn_profile_stages": ([vp, vp, d, ctypes.c_int64, dp], st),
+        "sgn_spacing": ([vp, dp, dp], st),
+        "sgn_last_error": ([vp], ctypes.c_char_p),
+        "sgn_status_string": ([ctypes.c_int32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def status_name(status: int) -> str:
+    try:
+        return load_library().sgn_status_string(status).decode()
+    except Exception:  # pragma: no cover - only when the library itself is unavailable
+        return str(status)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _require_gpu():
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("the SGN solver runs only on a ROCm GPU (torch.cuda.is_available() is False)")
+
+
+class Solver:
+    """One C-ABI context for one grid, storage type and stream.
+
+    ``grid`` is any object with nx, ny, xmin, xmax, ymin, ymax, bc_x, bc_y, g, lam
+    (e.g. :class:`paper_2601_02540_amd.workloads.Grid`).
+    """
+
+    def __init__(self, grid, dtype=None, source: int = SGN_SRC_NONE, device: Optional[int] = None):
+        torch = _torch()
+        _require_gpu()
+        self.lib = load_library()
+        self.grid = grid
+        self.dtype = torch.float64 if dtype is None else dtype
+        if self.dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be torch.float64 or torch.float32")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            p = SgnParams(grid.nx, grid.ny, grid.xmin, grid.xmax, grid.ymin, grid.ymax, grid.bc_x, grid.bc_y,
+                          grid.g, grid.lam, SGN_F64 if self.dtype == torch.float64 else SGN_F32, source)
+            ctx = ctypes.c_void_p()
+            s = self.lib.sgn_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+            if s != 0:
+                raise SgnError(s, self.lib.sgn_last_error(None).decode())
+        self.ctx = ctx
+        self.shape = (5, grid.ny, grid.nx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.sgn_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def _chk(self, s: int):
+        if s != 0:
+            raise SgnError(s, self.lib.sgn_last_error(self.ctx).decode())
+
+    def _state(self, q, name="q"):
+        if tuple(q.shape) != self.shape or q.dtype != self.dtype or not q.is_contiguous() or q.device != self.device:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
+        return ctypes.c_void_p(q.data_ptr())
+
+    def _plane(self, b, name="b"):
+        if tuple(b.shape) != self.shape[1:] or b.dtype != self.dtype or not b.is_contiguous() or b.device != self.device:
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {self.shape[1:]} on {self.device}")
+        return ctypes.c_void_p(b.data_ptr())
+
+    def empty_state(self):
+        return _torch().empty(self.shape, dtype=self.dtype, device=self.device)
+
+    # -- API ---------------------------------------------------------------
+    def spacing(self) -> Tuple[float, float]:
+        dx, dy = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sgn_spacing(self.ctx, ctypes.byref(dx), ctypes.byref(dy)))
+        return dx.value, dy.value
+
+    def set_bathymetry(self, b):
+        self._chk(self.lib.sgn_set_bathymetry(self.ctx, self._plane(b)))
+        self._b = b  # the copy is asynchronous: keep the source alive until the stream passes it
+
+    def init_aux(self, q):
+        self._chk(self.lib.sgn_init_aux(self.ctx, self._state(q)))
+        return q
+
+    def rhs(self, q, dq=None, t: float = 0.0):
+        if dq is None:
+            dq = self.empty_state()
+        self._chk(self.lib.sgn_rhs(self.ctx, self._state(q), self._state(dq, "dq"), float(t)))
+        return dq
+
+    def step(self, q, dt: float, nsteps: int = 1, t0: float = 0.0):
+        self._chk(self.lib.sgn_step(self.ctx, self._state(q), float(dt), int(nsteps), float(t0)))
+        return q
+
+    def mass_energy(self, q) -> Tuple[float, float]:
+        m, e = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sgn_mass_energy(self.ctx, self._state(q), ctypes.byref(m), ctypes.byref(e)))
+        return m.value, e.value
+
+    def mass(self, q) -> float:
+        m = ctypes.c_double()
+        self._chk(self.lib.sgn_mass(self.ctx, self._state(q), ctypes.byref(m)))
+        return m.value
+
+    def energy(self, q) -> float:
+        e = ctypes.c_double()
+        self._chk(self.lib.sgn_energy(self.ctx, self._state(q), ctypes.byref(e)))
+        return e.value
+
+    def rates(self, q) -> Tuple[float, float]:
+        mr, er = ctypes.c_double(), ctypes.c_double()
+        self._chk(self.lib.sgn_rates(self.ctx, self._state(q), ctypes.byref(mr), ctypes.byref(er)))
+        return mr.value, er.value
+
+    def cfl_dt(self, q, cfl: float = 0.5) -> float:
+        dt = ctypes.c_double()
+        self._chk(self.lib.sgn_cfl_dt(self.ctx, self._state(q), float(cfl), ctypes.byref(dt)))
+        return dt.value
+
+    def profile_stages(self, q, dt: float, nsteps: int):
+        """Mean duration (ms) of each of the four stage kernels over nsteps steps."""
+        ms = (ctypes.c_double * 4)()
+        self._chk(self.lib.sgn_profile_stages(self.ctx, self._state(q), float(dt), int(nsteps), ms))
+        return list(ms)
+
+    def check(self):
+        self._chk(self.lib.sgn_check(self.ctx))

@@ -1,0 +1,480 @@
+// sgn_lib.hip -- C ABI of include/sgn.h: context, validation, launches, graphs.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sgn.h"
+#include "sgn_reduce.hpp"
+#include "sgn_stage.hpp"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Stage tile height used by rhs() and step().
+constexpr int STAGE_TY = 8;
+// Steps captured per graph replay.
+constexpr int GRAPH_STEPS = 8;
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void* q = nullptr;
+  double dt = 0.0;
+  int steps = 0;
+};
+
+}  // namespace
+
+struct sgn_ctx {
+  sgn_params p{};
+  sgn::GridConst gc{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  size_t N = 0;
+  size_t esize = 0;
+  void* b = nullptr;
+  void* acc = nullptr;
+  void* ya = nullptr;
+  void* yb = nullptr;
+  double* partials = nullptr;
+  double* result = nullptr;
+  double* host_result = nullptr;
+  int* flag = nullptr;
+  int* host_flag = nullptr;
+  bool b_set = false;
+  GraphCache graphs[2];
+  std::string err;
+};
+
+namespace {
+
+sgn_status fail(sgn_ctx* c, sgn_status st, const std::string& msg) {
+  if (c)
+    c->err = msg;
+  else
+    g_create_error = msg;
+  return st;
+}
+
+sgn_status hip_fail(sgn_ctx* c, hipError_t e, const char* what) {
+  return fail(c, SGN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                  \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
+  } while (0)
+
+double axis_spacing(int n, double lo, double hi, int bc) {
+  return bc == SGN_PERIODIC ? (hi - lo) / n : (hi - lo) / (n - 1);
+}
+
+void destroy_graphs(sgn_ctx* c) {
+  for (auto& g : c->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = GraphCache{};
+  }
+}
+
+int reduce_blocks(const sgn_ctx* c) { return c->p.ny < sgn::RED_MAX_BLOCKS ? c->p.ny : sgn::RED_MAX_BLOCKS; }
+
+// ---------------------------------------------------------------------------
+// Stage launches
+
+template <typename T, int MODE>
+hipError_t launch_stage_t(const sgn_ctx* c, hipStream_t s, const void* Y, const void* qn, void* acc, void* out,
+                          double c_acc, double c_y, double t) {
+  constexpr int TY = STAGE_TY;
+  const int ntx = (c->p.nx + sgn::TILE_X - 1) / sgn::TILE_X;
+  const int nty = (c->p.ny + TY - 1) / TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
+  const bool src = c->p.source == SGN_SRC_MMS;
+  const T* Yp = (const T*)Y;
+  const T* bp = (const T*)c->b;
+  const T* qp = (const T*)qn;
+  T* ap = (T*)acc;
+  T* op = (T*)out;
+#define SGN_LAUNCH(BX, BY, S)                                                                             \
+  hipLaunchKernelGGL((sgn::stage_kernel<T, BX, BY, MODE, S, TY>), grid, block, 0, s, c->gc, Yp, bp, qp, ap, op, \
+                     (T)c_acc, (T)c_y, t, c->flag)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (!src) {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, false);
+    else SGN_LAUNCH(1, 1, false);
+  } else {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, true);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, true);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, true);
+    else SGN_LAUNCH(1, 1, true);
+  }
+#undef SGN_LAUNCH
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t launch_stage(const sgn_ctx* c, hipStream_t s, const void* Y, const void* qn, void* acc, void* out,
+                        double c_acc, double c_y, double t) {
+  if (c->p.dtype == SGN_F64) return launch_stage_t<double, MODE>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+  return launch_stage_t<float, MODE>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+}
+
+// One classical RK4 step in three-register form (q, acc, and two stage planes):
+//   k1 = f(q),  acc = q + dt/6 k1,   Ya = q + dt/2 k1
+//   k2 = f(Ya), acc += dt/3 k2,      Yb = q + dt/2 k2
+//   k3 = f(Yb), acc += dt/3 k3,      Ya = q + dt k3
+//   k4 = f(Ya), q = acc + dt/6 k4
+hipError_t enqueue_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, double t) {
+  hipError_t e;
+  if ((e = launch_stage<sgn::MODE_FIRST>(c, s, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t))) return e;
+  if ((e = launch_stage<sgn::MODE_MID>(c, s, c->ya, q, c->acc, c->yb, dt / 3.0, dt / 2.0, t + dt / 2.0))) return e;
+  if ((e = launch_stage<sgn::MODE_MID>(c, s, c->yb, q, c->acc, c->ya, dt / 3.0, dt, t + dt / 2.0))) return e;
+  return launch_stage<sgn::MODE_LAST>(c, s, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
+}
+
+sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGraphExec_t* out) {
+  GraphCache& g = c->graphs[slot];
+  if (g.exec && g.q == q && g.dt == dt && g.steps == steps) {
+    *out = g.exec;
+    return SGN_OK;
+  }
+  if (g.exec) {
+    (void)hipGraphExecDestroy(g.exec);
+    g = GraphCache{};
+  }
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < steps && le == hipSuccess; ++k) le = enqueue_step(c, c->cap_stream, q, dt, 0.0);
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_fail(c, le, "stage launch during capture");
+  }
+  if (ce != hipSuccess) return hip_fail(c, ce, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return hip_fail(c, ie, "hipGraphInstantiate");
+  g.exec = exec;
+  g.q = q;
+  g.dt = dt;
+  g.steps = steps;
+  *out = exec;
+  return SGN_OK;
+}
+
+// Copies the health flag and `nres` result doubles to host, synchronizes, and
+// converts a raised flag into a status (clearing it).
+sgn_status sync_results(sgn_ctx* c, int nres) {
+  if (nres > 0) HIPCHK(c, hipMemcpyAsync(c->host_result, c->result, nres * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->host_flag, c->flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int f = *c->host_flag;
+  if (f) {
+    HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f & sgn::FLAG_NONFINITE) return fail(c, SGN_E_NONFINITE, "a step produced a non-finite value");
+    return fail(c, SGN_E_NONPOS_DEPTH, "a step produced h <= 0 (the method has no wetting/drying)");
+  }
+  return SGN_OK;
+}
+
+template <typename T>
+hipError_t launch_totals(const sgn_ctx* c, const void* q, const void* dq, int what) {
+  const int nb = reduce_blocks(c);
+  if (what == 0)
+    hipLaunchKernelGGL((sgn::totals_partial<T, 0>), dim3(nb), dim3(sgn::RED_THREADS), 0, c->stream, c->gc,
+                       (const T*)q, (const T*)c->b, (const T*)nullptr, c->partials);
+  else
+    hipLaunchKernelGGL((sgn::totals_partial<T, 1>), dim3(nb), dim3(sgn::RED_THREADS), 0, c->stream, c->gc,
+                       (const T*)q, (const T*)c->b, (const T*)dq, c->partials);
+  hipLaunchKernelGGL(sgn::totals_final, dim3(1), dim3(sgn::RED_THREADS), 0, c->stream, c->partials, nb, c->result);
+  return hipGetLastError();
+}
+
+sgn_status check_ctx(sgn_ctx* c, bool need_b) {
+  if (!c) return SGN_E_ARG;
+  if (need_b && !c->b_set) return fail(c, SGN_E_STATE, "bathymetry not set (call sgn_set_bathymetry first)");
+  return SGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sgn_status_string(int32_t s) {
+  switch (s) {
+    case SGN_OK: return "SGN_OK";
+    case SGN_E_ARG: return "SGN_E_ARG";
+    case SGN_E_SHAPE: return "SGN_E_SHAPE";
+    case SGN_E_UNSUPPORTED: return "SGN_E_UNSUPPORTED";
+    case SGN_E_HIP: return "SGN_E_HIP";
+    case SGN_E_NONPOS_DEPTH: return "SGN_E_NONPOS_DEPTH";
+    case SGN_E_NONFINITE: return "SGN_E_NONFINITE";
+    case SGN_E_ALLOC: return "SGN_E_ALLOC";
+    case SGN_E_STATE: return "SGN_E_STATE";
+    default: return "SGN_E_UNKNOWN";
+  }
+}
+
+const char* sgn_last_error(const sgn_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
+  if (!out) return fail(nullptr, SGN_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!p) return fail(nullptr, SGN_E_ARG, "params is NULL");
+  if (p->nx < 4 || p->ny < 4) return fail(nullptr, SGN_E_SHAPE, "each axis needs at least 4 nodes");
+  if (!(std::isfinite(p->xmin) && std::isfinite(p->xmax) && p->xmax > p->xmin && std::isfinite(p->ymin) &&
+        std::isfinite(p->ymax) && p->ymax > p->ymin))
+    return fail(nullptr, SGN_E_SHAPE, "domain bounds must be finite with max > min");
+  if ((p->bc_x != SGN_PERIODIC && p->bc_x != SGN_REFLECTING) || (p->bc_y != SGN_PERIODIC && p->bc_y != SGN_REFLECTING))
+    return fail(nullptr, SGN_E_ARG, "unknown boundary type");
+  if (!(std::isfinite(p->g) && p->g > 0.0)) return fail(nullptr, SGN_E_ARG, "g must be finite and > 0");
+  if (!(std::isfinite(p->lambda) && p->lambda >= 0.0)) return fail(nullptr, SGN_E_ARG, "lambda must be finite and >= 0");
+  if (p->dtype != SGN_F64 && p->dtype != SGN_F32) return fail(nullptr, SGN_E_ARG, "unknown dtype");
+  if (p->source != SGN_SRC_NONE && p->source != SGN_SRC_MMS) return fail(nullptr, SGN_E_ARG, "unknown source");
+  const size_t N = (size_t)p->nx * (size_t)p->ny;
+  if (N > ((size_t)1 << 40)) return fail(nullptr, SGN_E_SHAPE, "grid too large");
+
+  sgn_ctx* c = new sgn_ctx();
+  c->p = *p;
+  c->N = N;
+  c->esize = p->dtype == SGN_F64 ? sizeof(double) : sizeof(float);
+  c->stream = (hipStream_t)stream;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipGetDevice");
+  }
+  sgn::GridConst& gc = c->gc;
+  gc.nx = p->nx;
+  gc.ny = p->ny;
+  gc.bc_x = p->bc_x;
+  gc.bc_y = p->bc_y;
+  gc.dx = axis_spacing(p->nx, p->xmin, p->xmax, p->bc_x);
+  gc.dy = axis_spacing(p->ny, p->ymin, p->ymax, p->bc_y);
+  gc.inv2dx = 1.0 / (2.0 * gc.dx);
+  gc.inv2dy = 1.0 / (2.0 * gc.dy);
+  gc.invdx = 1.0 / gc.dx;
+  gc.invdy = 1.0 / gc.dy;
+  gc.xmin = p->xmin;
+  gc.ymin = p->ymin;
+  gc.g = p->g;
+  gc.lam = p->lambda;
+
+  const size_t plane = N * c->esize;
+  bool ok = hipMalloc(&c->b, plane) == hipSuccess && hipMalloc(&c->acc, 5 * plane) == hipSuccess &&
+            hipMalloc(&c->ya, 5 * plane) == hipSuccess && hipMalloc(&c->yb, 5 * plane) == hipSuccess &&
+            hipMalloc((void**)&c->partials, 4 * sgn::RED_MAX_BLOCKS * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->result, 8 * sizeof(double)) == hipSuccess &&
+            hipMalloc((void**)&c->flag, sizeof(int)) == hipSuccess &&
+            hipHostMalloc((void**)&c->host_result, 8 * sizeof(double), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void**)&c->host_flag, sizeof(int), hipHostMallocDefault) == hipSuccess &&
+            hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    sgn_destroy(c);
+    return fail(nullptr, SGN_E_ALLOC, "device allocation failed");
+  }
+  if (hipMemsetAsync(c->flag, 0, sizeof(int), c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    sgn_destroy(c);
+    return fail(nullptr, SGN_E_HIP, "initial flag clear failed");
+  }
+  *out = c;
+  return SGN_OK;
+}
+
+sgn_status sgn_destroy(sgn_ctx* c) {
+  if (!c) return SGN_OK;
+  (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->b) (void)hipFree(c->b);
+  if (c->acc) (void)hipFree(c->acc);
+  if (c->ya) (void)hipFree(c->ya);
+  if (c->yb) (void)hipFree(c->yb);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->result) (void)hipFree(c->result);
+  if (c->flag) (void)hipFree(c->flag);
+  if (c->host_result) (void)hipHostFree(c->host_result);
+  if (c->host_flag) (void)hipHostFree(c->host_flag);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  delete c;
+  return SGN_OK;
+}
+
+sgn_status sgn_set_stream(sgn_ctx* c, void* stream) {
+  if (!c) return SGN_E_ARG;
+  c->stream = (hipStream_t)stream;
+  destroy_graphs(c);
+  return SGN_OK;
+}
+
+sgn_status sgn_spacing(const sgn_ctx* c, double* dx, double* dy) {
+  if (!c || !dx || !dy) return SGN_E_ARG;
+  *dx = c->gc.dx;
+  *dy = c->gc.dy;
+  return SGN_OK;
+}
+
+sgn_status sgn_set_bathymetry(sgn_ctx* c, const void* b) {
+  if (!c) return SGN_E_ARG;
+  if (!b) return fail(c, SGN_E_ARG, "b is NULL");
+  HIPCHK(c, hipMemcpyAsync(c->b, b, c->N * c->esize, hipMemcpyDeviceToDevice, c->stream));
+  c->b_set = true;
+  return SGN_OK;
+}
+
+sgn_status sgn_init_aux(sgn_ctx* c, void* q) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q) return fail(c, SGN_E_ARG, "q is NULL");
+  const dim3 grid((c->p.nx + 63) / 64, (c->p.ny + 3) / 4), block(256);
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(sgn::init_aux_kernel<double>, grid, block, 0, c->stream, c->gc, (double*)q, (const double*)c->b);
+  else
+    hipLaunchKernelGGL(sgn::init_aux_kernel<float>, grid, block, 0, c->stream, c->gc, (float*)q, (const float*)c->b);
+  HIPCHK(c, hipGetLastError());
+  return SGN_OK;
+}
+
+sgn_status sgn_rhs(sgn_ctx* c, const void* q, void* dq, double t) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q || !dq) return fail(c, SGN_E_ARG, "q or dq is NULL");
+  if (q == dq) return fail(c, SGN_E_ARG, "q and dq must not overlap");
+  if (!std::isfinite(t)) return fail(c, SGN_E_ARG, "t must be finite");
+  HIPCHK(c, launch_stage<sgn::MODE_RHS>(c, c->stream, q, nullptr, nullptr, dq, 0.0, 0.0, t));
+  return SGN_OK;
+}
+
+sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q) return fail(c, SGN_E_ARG, "q is NULL");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, SGN_E_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(c, SGN_E_ARG, "nsteps must be >= 0");
+  if (!std::isfinite(t0)) return fail(c, SGN_E_ARG, "t0 must be finite");
+  if (nsteps == 0) return SGN_OK;
+  if (c->p.source != SGN_SRC_NONE) {
+    // Stage times matter: launch directly.
+    for (int64_t s = 0; s < nsteps; ++s) HIPCHK(c, enqueue_step(c, c->stream, q, dt, t0 + (double)s * dt));
+    return SGN_OK;
+  }
+  int64_t left = nsteps;
+  if (left >= GRAPH_STEPS) {
+    hipGraphExec_t ge;
+    if ((st = get_graph(c, 0, q, dt, GRAPH_STEPS, &ge))) return st;
+    for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIPCHK(c, hipGraphLaunch(ge, c->stream));
+  }
+  if (left > 0) {
+    hipGraphExec_t g1;
+    if ((st = get_graph(c, 1, q, dt, 1, &g1))) return st;
+    for (; left > 0; --left) HIPCHK(c, hipGraphLaunch(g1, c->stream));
+  }
+  return SGN_OK;
+}
+
+sgn_status sgn_mass_energy(sgn_ctx* c, const void* q, double* mass, double* energy) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q) return fail(c, SGN_E_ARG, "q is NULL");
+  hipError_t e = c->p.dtype == SGN_F64 ? launch_totals<double>(c, q, nullptr, 0) : launch_totals<float>(c, q, nullptr, 0);
+  HIPCHK(c, e);
+  if ((st = sync_results(c, 2))) return st;
+  if (mass) *mass = c->host_result[0];
+  if (energy) *energy = c->host_result[1];
+  return SGN_OK;
+}
+
+sgn_status sgn_mass(sgn_ctx* c, const void* q, double* out) {
+  if (!out) return c ? fail(c, SGN_E_ARG, "out is NULL") : SGN_E_ARG;
+  return sgn_mass_energy(c, q, out, nullptr);
+}
+
+sgn_status sgn_energy(sgn_ctx* c, const void* q, double* out) {
+  if (!out) return c ? fail(c, SGN_E_ARG, "out is NULL") : SGN_E_ARG;
+  return sgn_mass_energy(c, q, nullptr, out);
+}
+
+sgn_status sgn_rates(sgn_ctx* c, const void* q, double* mass_rate, double* energy_rate) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q) return fail(c, SGN_E_ARG, "q is NULL");
+  if (c->p.source != SGN_SRC_NONE) return fail(c, SGN_E_UNSUPPORTED, "rates are defined without source terms");
+  HIPCHK(c, launch_stage<sgn::MODE_RHS>(c, c->stream, q, nullptr, nullptr, c->acc, 0.0, 0.0, 0.0));
+  hipError_t e = c->p.dtype == SGN_F64 ? launch_totals<double>(c, q, c->acc, 1) : launch_totals<float>(c, q, c->acc, 1);
+  HIPCHK(c, e);
+  if ((st = sync_results(c, 2))) return st;
+  if (mass_rate) *mass_rate = c->host_result[0];
+  if (energy_rate) *energy_rate = c->host_result[1];
+  return SGN_OK;
+}
+
+sgn_status sgn_cfl_dt(sgn_ctx* c, const void* q, double cfl, double* dt) {
+  sgn_status st = check_ctx(c, false);
+  if (st) return st;
+  if (!q || !dt) return fail(c, SGN_E_ARG, "q or dt is NULL");
+  if (!(std::isfinite(cfl) && cfl > 0.0)) return fail(c, SGN_E_ARG, "cfl must be finite and > 0");
+  const int nb = reduce_blocks(c);
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(sgn::speed_partial<double>, dim3(nb), dim3(sgn::RED_THREADS), 0, c->stream, c->gc,
+                       (const double*)q, c->partials);
+  else
+    hipLaunchKernelGGL(sgn::speed_partial<float>, dim3(nb), dim3(sgn::RED_THREADS), 0, c->stream, c->gc,
+                       (const float*)q, c->partials);
+  hipLaunchKernelGGL(sgn::speed_final, dim3(1), dim3(sgn::RED_THREADS), 0, c->stream, c->partials, nb, c->result);
+  HIPCHK(c, hipGetLastError());
+  if ((st = sync_results(c, 1))) return st;
+  const double m = c->host_result[0];
+  if (!(std::isfinite(m) && m > 0.0)) return fail(c, SGN_E_NONFINITE, "characteristic speed is not finite and positive");
+  *dt = cfl / m;
+  return SGN_OK;
+}
+
+sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, double* ms) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q || !ms) return fail(c, SGN_E_ARG, "q or ms is NULL");
+  if (!(std::isfinite(dt) && dt > 0.0) || nsteps <= 0) return fail(c, SGN_E_ARG, "dt must be > 0 and nsteps > 0");
+  hipEvent_t ev[5];
+  for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventCreate(&ev[k]));
+  double acc_ms[4] = {0, 0, 0, 0};
+  hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
+    const double t = (double)s * dt;
+    e = hipEventRecord(ev[0], c->stream);
+    if (!e) e = launch_stage<sgn::MODE_FIRST>(c, c->stream, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t);
+    if (!e) e = hipEventRecord(ev[1], c->stream);
+    if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->ya, q, c->acc, c->yb, dt / 3.0, dt / 2.0, t + dt / 2.0);
+    if (!e) e = hipEventRecord(ev[2], c->stream);
+    if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->yb, q, c->acc, c->ya, dt / 3.0, dt, t + dt / 2.0);
+    if (!e) e = hipEventRecord(ev[3], c->stream);
+    if (!e) e = launch_stage<sgn::MODE_LAST>(c, c->stream, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
+    if (!e) e = hipEventRecord(ev[4], c->stream);
+    if (!e) e = hipEventSynchronize(ev[4]);
+    for (int k = 0; k < 4 && !e; ++k) {
+      float m = 0.f;
+      e = hipEventElapsedTime(&m, ev[k], ev[k + 1]);
+      acc_ms[k] += m;
+    }
+  }
+  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+  if (e != hipSuccess) return hip_fail(c, e, "profiled step");
+  for (int k = 0; k < 4; ++k) ms[k] = acc_ms[k] / (double)nsteps;
+  return sync_results(c, 0);
+}
+
+sgn_status sgn_check(sgn_ctx* c) {
+  if (!c) return SGN_E_ARG;
+  return sync_results(c, 0);
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+// sgn_stage.hpp -- the fused right-hand-side + Runge-Kutta stage kernel.
+//
+// One workgroup of 256 threads (four wave64s) owns a tile of 64 x TY nodes.
+// It stages the tile plus a one-node halo of the six input planes
+// (h, u, v, w, eta, b) and of 1/h in LDS, with the periodic wrap or the
+// reflecting clamp applied while loading.  Each thread then evaluates the
+// split-form rates of eq. (sd_periodic_2D_SGN) / eq. (semi_2D) for TY/4 nodes
+// of one column, with the one-sided closure rows and the wall SATs of Remark
+// "Concrete SBP operators and SATs" resolved per node, and applies the stage
+// update in registers.  Products that are differentiated (h(h+b), u^2, hu,
+// huv, eta^2/h, huw, ...) are formed at the two neighbours from LDS values, so
+// only one reciprocal per node is computed.
+#pragma once
+
+#include "sgn_common.hpp"
+#include "sgn_mms.hpp"
+
+namespace sgn {
+
+constexpr int TILE_X = 64;
+constexpr int STAGE_THREADS = 256;
+constexpr int THREAD_ROWS = STAGE_THREADS / TILE_X;  // 4
+
+// Neighbour selection along one axis for node index i of n: the left/right
+// LDS offsets (relative to the node) and the derivative scale.  Interior and
+// periodic rows use (f[i+1] - f[i-1]) / (2 d); reflecting first/last rows use
+// (f[1] - f[0]) / d and (f[n-1] - f[n-2]) / d.
+template <int BC>
+struct AxisStencil {
+  int om, op;
+  double scale;
+  __device__ __forceinline__ AxisStencil(int i, int n, double inv2d, double invd) {
+    om = -1;
+    op = 1;
+    scale = inv2d;
+    if (BC == BC_REFLECTING) {
+      if (i == 0) {
+        om = 0;
+        scale = invd;
+      }
+      if (i == n - 1) {
+        op = 0;
+        scale = invd;
+      }
+    }
+  }
+};
+
+template <typename T>
+struct Node {
+  T h, u, v, w, eta, b, ih;  // ih = 1/h
+};
+
+template <typename T, int TY>
+struct StageSmem {
+  T f[7][TY + 2][TILE_X + 2];  // h u v w eta b 1/h
+};
+
+template <typename T, int TY>
+__device__ __forceinline__ Node<T> lds_node(const StageSmem<T, TY>& s, int r, int c) {
+  Node<T> n;
+  n.h = s.f[0][r][c];
+  n.u = s.f[1][r][c];
+  n.v = s.f[2][r][c];
+  n.w = s.f[3][r][c];
+  n.eta = s.f[4][r][c];
+  n.b = s.f[5][r][c];
+  n.ih = s.f[6][r][c];
+  return n;
+}
+
+// Rates of the five evolved variables at one node given its value, its four
+// neighbours (already resolved for closures) and the derivative scales.
+template <typename T>
+struct Rates {
+  T h, u, v, w, eta;
+};
+
+template <typename T>
+__device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Node<T>& xm, const Node<T>& xp,
+                                                     const Node<T>& ym, const Node<T>& yp, T sx, T sy, T g, T lam,
+                                                     T satx_coef, T saty_coef) {
+  const T half = T(0.5);
+  // x derivatives (12)
+  const T Dxh = sx * (xp.h - xm.h);
+  const T Dxu = sx * (xp.u - xm.u);
+  const T Dxv = sx * (xp.v - xm.v);
+  const T Dxw = sx * (xp.w - xm.w);
+  const T Dxeta = sx * (xp.eta - xm.eta);
+  const T Dxb = sx * (xp.b - xm.b);
+  const T DxhH = sx * (xp.h * (xp.h + xp.b) - xm.h * (xm.h + xm.b));
+  const T Dxu2 = sx * (xp.u * xp.u - xm.u * xm.u);
+  const T xphu = xp.h * xp.u, xmhu = xm.h * xm.u;
+  const T Dxhu = sx * (xphu - xmhu);
+  const T Dxhuv = sx * (xphu * xp.v - xmhu * xm.v);
+  const T Dxe2h = sx * (xp.eta * xp.eta * xp.ih - xm.eta * xm.eta * xm.ih);
+  const T Dxhuw = sx * (xphu * xp.w - xmhu * xm.w);
+  // y derivatives (12)
+  const T Dyh = sy * (yp.h - ym.h);
+  const T Dyu = sy * (yp.u - ym.u);
+  const T Dyv = sy * (yp.v - ym.v);
+  const T Dyw = sy * (yp.w - ym.w);
+  const T Dyeta = sy * (yp.eta - ym.eta);
+  const T Dyb = sy * (yp.b - ym.b);
+  const T DyhH = sy * (yp.h * (yp.h + yp.b) - ym.h * (ym.h + ym.b));
+  const T Dyv2 = sy * (yp.v * yp.v - ym.v * ym.v);
+  const T yphv = yp.h * yp.v, ymhv = ym.h * ym.v;
+  const T Dyhv = sy * (yphv - ymhv);
+  const T Dyhuv = sy * (yphv * yp.u - ymhv * ym.u);
+  const T Dye2h = sy * (yp.eta * yp.eta * yp.ih - ym.eta * ym.eta * ym.ih);
+  const T Dyhvw = sy * (yphv * yp.w - ymhv * ym.w);
+
+  const T h = c.h, u = c.u, v = c.v, w = c.w, eta = c.eta;
+  const T H = h + c.b;
+  const T r = eta * c.ih;
+  const T omr = T(1) - r;
+  const T hu = h * u, hv = h * v, uv = u * v, hw = h * w;
+  const T lam6 = lam * T(1.0 / 6.0), lam3 = lam * T(1.0 / 3.0), lam2 = lam * T(0.5);
+
+  Rates<T> k;
+  k.h = -(u * Dxh + h * Dxu + v * Dyh + h * Dyv) + satx_coef * hu + saty_coef * hv;
+
+  const T A = g * (DxhH - H * Dxh) +
+              half * (h * Dxu2 - u * u * Dxh + u * Dxhu - hu * Dxu + Dyhuv - uv * Dyh + hv * Dyu - hu * Dyv) +
+              lam6 * (r * r * Dxh - Dxe2h) + lam3 * omr * Dxeta + lam2 * omr * Dxb;
+  const T B = g * (DyhH - H * Dyh) +
+              half * (h * Dyv2 - v * v * Dyh + v * Dyhv - hv * Dyv + Dxhuv - uv * Dxh + hu * Dxv - hv * Dxu) +
+              lam6 * (r * r * Dyh - Dye2h) + lam3 * omr * Dyeta + lam2 * omr * Dyb;
+  const T C = half * (Dxhuw + hu * Dxw - u * w * Dxh - hw * Dxu + Dyhvw + hv * Dyw - v * w * Dyh - hw * Dyv);
+  k.u = -A * c.ih;
+  k.v = -B * c.ih;
+  k.w = (lam * omr - C) * c.ih;
+  k.eta = w - (u * Dxeta + v * Dyeta + T(1.5) * (u * Dxb + v * Dyb));
+  return k;
+}
+
+template <typename T, int BCX, int BCY, int MODE, bool SRC, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const GridConst gc, const T* __restrict__ Y,
+                                                              const T* __restrict__ bplane,
+                                                              const T* __restrict__ qn, T* __restrict__ acc,
+                                                              T* __restrict__ out, T c_acc, T c_y, double t,
+                                                              int* __restrict__ flag) {
+  static_assert(TY % THREAD_ROWS == 0, "tile height must be a multiple of 4");
+  constexpr int RPT = TY / THREAD_ROWS;
+  constexpr int W = TILE_X + 2;
+  constexpr int REGION = (TY + 2) * W;
+  __shared__ StageSmem<T, TY> s;
+
+  const int nx = gc.nx, ny = gc.ny;
+  const size_t N = (size_t)nx * (size_t)ny;
+  const int ntx = (nx + TILE_X - 1) / TILE_X;
+  const int nty = (ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  const int i0 = (tile % ntx) * TILE_X;
+  const int j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  const int tx = tid & (TILE_X - 1);
+  const int ty = tid >> 6;
+
+  // Stage the tile and its halo.  Periodic axes wrap, reflecting axes clamp
+  // (clamped halo values are never used: the closure rows are one-sided).
+  for (int idx = tid; idx < REGION; idx += STAGE_THREADS) {
+    const int rr = idx / W;
+    const int cc = idx - rr * W;
+    int gi = i0 - 1 + cc;
+    int gj = j0 - 1 + rr;
+    if (BCX == BC_PERIODIC) {
+      gi = gi < 0 ? gi + nx : gi;
+      gi = gi >= nx ? gi - nx : gi;
+      gi = gi >= nx ? gi % nx : gi;
+    } else {
+      gi = gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi);
+    }
+    if (BCY == BC_PERIODIC) {
+      gj = gj < 0 ? gj + ny : gj;
+      gj = gj >= ny ? gj - ny : gj;
+      gj = gj >= ny ? gj % ny : gj;
+    } else {
+      gj = gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj);
+    }
+    const size_t o = (size_t)gj * nx + gi;
+    const T h = Y[o];
+    s.f[0][rr][cc] = h;
+    s.f[1][rr][cc] = Y[N + o];
+    s.f[2][rr][cc] = Y[2 * N + o];
+    s.f[3][rr][cc] = Y[3 * N + o];
+    s.f[4][rr][cc] = Y[4 * N + o];
+    s.f[5][rr][cc] = bplane[o];
+    s.f[6][rr][cc] = T(1) / h;
+  }
+
+  // Own-node operands of the stage update, fetched before the barrier so the
+  // loads overlap the LDS staging.
+  const int i = i0 + tx;
+  T pre[RPT][5];
+  T pacc[RPT][5];
+  if (MODE == MODE_MID || MODE == MODE_LAST) {
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int j = j0 + ty + k * THREAD_ROWS;
+      if (i < nx && j < ny) {
+        const size_t o = (size_t)j * nx + i;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          pacc[k][f] = acc[f * N + o];
+          if (MODE == MODE_MID) pre[k][f] = qn[f * N + o];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  const T g = T(gc.g), lam = T(gc.lam);
+  const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
+  T satx = T(0);
+  if (BCX == BC_REFLECTING) {
+    if (i == 0) satx = T(-2.0 * gc.invdx);
+    if (i == nx - 1) satx = T(2.0 * gc.invdx);
+  }
+  int health = 0;
+
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = ty + k * THREAD_ROWS;
+    const int j = j0 + lr;
+    if (i >= nx || j >= ny) continue;
+    const AxisStencil<BCY> ay(j, ny, gc.inv2dy, gc.invdy);
+    T saty = T(0);
+    if (BCY == BC_REFLECTING) {
+      if (j == 0) saty = T(-2.0 * gc.invdy);
+      if (j == ny - 1) saty = T(2.0 * gc.invdy);
+    }
+    const int r = lr + 1, cidx = tx + 1;
+    const Node<T> c = lds_node(s, r, cidx);
+    const Node<T> xm = lds_node(s, r, cidx + ax.om);
+    const Node<T> xp = lds_node(s, r, cidx + ax.op);
+    const Node<T> ym = lds_node(s, r + ay.om, cidx);
+    const Node<T> yp = lds_node(s, r + ay.op, cidx);
+    Rates<T> kk = split_form_rates<T>(c, xm, xp, ym, yp, T(ax.scale), T(ay.scale), g, lam, satx, saty);
+    if (SRC) {
+      double S[5];
+      mms_source(gc.xmin + i * gc.dx, gc.ymin + j * gc.dy, t, gc.g, S);
+      kk.h += T(S[0]);
+      kk.u += T(S[1]);
+      kk.v += T(S[2]);
+      kk.w += T(S[3]);
+      kk.eta += T(S[4]);
+    }
+    const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
+    const T yv[5] = {c.h, c.u, c.v, c.w, c.eta};
+    const size_t o = (size_t)j * nx + i;
+    if (MODE == MODE_RHS) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) out[f * N + o] = kv[f];
+    } else if (MODE == MODE_FIRST) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        acc[f * N + o] = yv[f] + c_acc * kv[f];
+        out[f * N + o] = yv[f] + c_y * kv[f];
+      }
+    } else if (MODE == MODE_MID) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        acc[f * N + o] = pacc[k][f] + c_acc * kv[f];
+        out[f * N + o] = pre[k][f] + c_y * kv[f];
+      }
+    } else {
+      T nv[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        nv[f] = pacc[k][f] + c_acc * kv[f];
+        out[f * N + o] = nv[f];
+      }
+      if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
+      const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
+      if (!isfinite(sum)) health |= FLAG_NONFINITE;
+    }
+  }
+  if (MODE == MODE_LAST && health) atomicOr(flag, health);
+}
+
+}  // namespace sgn

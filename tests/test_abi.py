@@ -1,0 +1,49 @@
+"""CPU-side checks of the boundary: the HIP library builds for gfx950, loads, and
+exports every function declared in include/sgn.h.  No compute call is made."""
+
+import ctypes
+import os
+
+import pytest
+
+from paper_2601_02540_amd import binding
+
+
+def test_header_declares_core_api():
+    syms = binding.header_symbols()
+    for name in ("sgn_create", "sgn_destroy", "sgn_set_bathymetry", "sgn_init_aux", "sgn_rhs", "sgn_step",
+                 "sgn_mass", "sgn_energy", "sgn_rates", "sgn_cfl_dt", "sgn_last_error"):
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2601_02540_amd import build
+        build.build()
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    missing = [s for s in binding.header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_library_targets_gfx950_only():
+    """The offload bundle inside the library carries gfx950 code objects."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("library not built")
+    data = open(binding.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    assert b"gfx942" not in data and b"gfx90a" not in data
+
+
+def test_status_strings_without_gpu():
+    lib = binding.load_library()
+    assert lib.sgn_status_string(0) == b"SGN_OK"
+    assert lib.sgn_status_string(-5) == b"SGN_E_NONPOS_DEPTH"
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2601_02540_amd import workloads as W
+    with pytest.raises(RuntimeError):
+        binding.Solver(W.Grid(8, 8, 0.0, 1.0, 0.0, 1.0))
