@@ -32,11 +32,14 @@ if ROOT not in sys.path:
 
 METRIC = "RK-stage cell-updates/s and % HBM peak (FP64 vs FP32); adjoint:forward cost"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic traffic of one fused RK4 step in three-register form, in values
-# per cell: stage 1 reads q, b and writes acc, Y (16); stages 2 and 3 read Y, b,
-# q, acc and write acc, Y (26 each); stage 4 reads Y, b, acc and writes q (16).
-VALUES_PER_STEP = 84
-VALUES_PER_STAGE = VALUES_PER_STEP / 4.0
+# Algorithmic HBM traffic of one RK4 step, in values per node, and kernel
+# launches per step, for each step path:
+#  pairs:  pair 1 reads q, b and writes acc, Yb (16); pair 2 reads Yb, b, q, acc
+#          and writes q_new (21)  -> 37 values, 2 launches
+#  stages: stage 1 reads q, b and writes acc, Y (16); stages 2 and 3 read Y, b,
+#          q, acc and write acc, Y (26 each); stage 4 reads Y, b, acc and writes
+#          q (16)                 -> 84 values, 4 launches
+PATHS = {"pairs": (37, 2), "stages": (84, 4)}
 
 
 def log(msg):
@@ -60,13 +63,17 @@ def lake_at_rest_energy(grid, b, mass):
     return 0.5 * grid.g * (M * (H * H - b * b)).sum()
 
 
-def run_gpu(problem, dtype, steps, warmup, label):
+def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
     import numpy as np
     import torch
     from paper_2601_02540_amd.binding import Solver
 
     grid = problem.grid
     s = Solver(grid, dtype)
+    s.set_step_path(path)
+    if tile_y is not None:
+        s.set_tile_y(tile_y)
+    values, launches = PATHS[path]
     b = torch.from_numpy(problem.b).to(dtype).cuda().contiguous()
     q = torch.from_numpy(problem.q0).to(dtype).cuda().contiguous()
     s.set_bathymetry(b)
@@ -90,8 +97,8 @@ def run_gpu(problem, dtype, steps, warmup, label):
     m1, e1 = s.mass_energy(q)
     cells = grid.nx * grid.ny
     esize = 8 if dtype == torch.float64 else 4
-    launch_s = sec / (4 * steps)
-    achieved = VALUES_PER_STAGE * esize * cells / launch_s / 1e9
+    launch_s = sec / (launches * steps)
+    achieved = values / launches * esize * cells / launch_s / 1e9
     # per-mode durations of the four stage kernels (direct launches with HIP events)
     ms = s.profile_stages(q, dt, 5)
     e_rest = lake_at_rest_energy(grid, problem.b.astype(np.float64), m0)
@@ -103,7 +110,10 @@ def run_gpu(problem, dtype, steps, warmup, label):
         "stage_launch_us": launch_s * 1e6,
         "achieved_GBs": achieved,
         "frac": achieved / HBM_PEAK_GBS,
-        "stage_ms_by_mode": {"first": ms[0], "mid1": ms[1], "mid2": ms[2], "last": ms[3]},
+        "path": path,
+        "tile_y": tile_y,
+        "kernel_ms": ({"pair1": ms[0], "pair2": ms[1]} if path == "pairs" else
+                      {"stage1": ms[0], "stage2": ms[1], "stage3": ms[2], "stage4": ms[3]}),
         "mass_drift_rel": (m1 - m0) / abs(m0),
         "energy_drift_rel": (e1 - e0) / abs(e0),
         "energy_drift_rel_to_excess": (e1 - e0) / abs(e0 - e_rest),
@@ -152,6 +162,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="grid nodes per axis")
     ap.add_argument("--no-variants", action="store_true", help="skip the reflecting and FP32 repeats")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--path", choices=sorted(PATHS), default="pairs", help="step path of the main run")
+    ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
+                    help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
     args = ap.parse_args()
 
@@ -174,16 +187,20 @@ def main():
     n = args.n
     log(f"[bench] generating {n}x{n} workload")
     prob = W.random_phase_large(n, W.PERIODIC, seed=3)
-    main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64")
+    P, T = args.path, args.tile_y
+    main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64", P, T)
 
     variants = {}
     if not args.no_variants:
-        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32")
+        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T)
         variants["periodic_f32"]["energy_diff_vs_f64_rel"] = (
             (variants["periodic_f32"]["energy_final"] - main_res["energy_final"]) / abs(main_res["energy_final"]))
         probr = W.random_phase_large(n, W.REFLECTING, seed=3)
-        variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64")
-        variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32")
+        variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T)
+        variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T)
+        other = "stages" if P == "pairs" else "pairs"
+        variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
+                                                    f"periodic f64 {other}", other, T)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -211,13 +228,15 @@ def main():
                    "dt": main_res["dt"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_res["frac"], "traffic": None,
-                     "kernel": "stage_kernel (fused RHS + RK4 stage; mean over the 4 stage launches of a step)",
-                     "algorithmic_bytes_per_cell_stage": VALUES_PER_STAGE * 8},
+                     "kernel": (f"pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)" if P == "pairs"
+                                else "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)"),
+                     "algorithmic_bytes_per_launch_per_node": PATHS[P][0] / PATHS[P][1] * 8,
+                     "algorithmic_bytes_per_step_per_node": PATHS[P][0] * 8},
         "cpu_baseline": cpu,
         "energy_drift_rel": main_res["energy_drift_rel"],
         "energy_drift_rel_to_excess": main_res["energy_drift_rel_to_excess"],
         "mass_drift_rel": main_res["mass_drift_rel"],
-        "stage_ms_by_mode": main_res["stage_ms_by_mode"],
+        "kernel_ms": main_res["kernel_ms"],
         "variants": {k: {kk: vv for kk, vv in v.items() if kk not in ("energy_final",)} for k, v in variants.items()},
     }
     print(json.dumps(line), flush=True)

@@ -87,6 +87,17 @@ typedef struct {
 
 typedef struct sgn_ctx sgn_ctx;
 
+/* Options (sgn_set_option).
+ * SGN_OPT_STEP_PATH: how sgn_step evaluates one RK4 step.
+ *   SGN_PATH_PAIRS (default): two kernels, each fusing two stages; the
+ *     intermediate stage stays in LDS.  37 values of HBM traffic per node and
+ *     step.  An odd final step runs on the four-stage path.
+ *   SGN_PATH_STAGES: four kernels, one per stage.  84 values per node and step.
+ * SGN_OPT_TILE_Y: tile height of the stage and pair kernels, 8 or 16 (default 8 for
+ *   SGN_F64, 16 for SGN_F32). */
+typedef enum { SGN_OPT_STEP_PATH = 0, SGN_OPT_TILE_Y = 1 } sgn_option;
+typedef enum { SGN_PATH_PAIRS = 0, SGN_PATH_STAGES = 1 } sgn_step_path;
+
 /* Create a context on the current HIP device.  stream is a hipStream_t (NULL
  * for the null stream).  Allocates the Runge-Kutta scratch (three states), a
  * bathymetry plane and the reduction partials.  On failure *out is NULL. */
@@ -97,6 +108,10 @@ sgn_status sgn_destroy(sgn_ctx* ctx);
 
 /* Change the stream later calls are enqueued on (invalidates captured graphs). */
 sgn_status sgn_set_stream(sgn_ctx* ctx, void* stream);
+
+/* Set an sgn_option (drops captured graphs).  SGN_E_ARG / SGN_E_UNSUPPORTED on
+ * unknown options or values. */
+sgn_status sgn_set_option(sgn_ctx* ctx, int32_t option, int64_t value);
 
 /* Copy the bathymetry b (device, one plane) into the context.  Required before
  * any call that evaluates the right-hand side or the energy. */
@@ -133,10 +148,11 @@ sgn_status sgn_rates(sgn_ctx* ctx, const void* q, double* mass_rate, double* ene
 /* dt = cfl / max_ij [(|u|+c)/dx + (|v|+c)/dy] with c^2 = g h + lambda eta^2/(3 h^2). */
 sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
 
-/* Measurement: advance q by nsteps RK4 steps exactly like sgn_step but with
- * direct launches, recording HIP events on the context's stream around each of
- * the four stage kernels.  ms[s] receives the mean duration of stage s
- * (0 = first, 1 and 2 = middle, 3 = last) in milliseconds.  Synchronizes. */
+/* Measurement: advance q by nsteps RK4 steps like sgn_step but with direct
+ * launches, recording HIP events on the context's stream around every kernel.
+ * Four-stage path: ms[s] = mean duration of stage kernel s (0 = first, 1 and 2
+ * = middle, 3 = last).  Pair path: ms[0] = pair 1, ms[1] = pair 2, ms[2] =
+ * ms[3] = 0 (an odd nsteps is rounded up).  Milliseconds; synchronizes. */
 sgn_status sgn_profile_stages(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* ms);
 
 /* Synchronize and report (then clear) the device health flag. */

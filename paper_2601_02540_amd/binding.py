@@ -20,6 +20,8 @@ HEADER_PATH = os.path.join(ROOT, "include", "sgn.h")
 
 SGN_F64, SGN_F32 = 0, 1
 SGN_SRC_NONE, SGN_SRC_MMS = 0, 1
+SGN_OPT_STEP_PATH, SGN_OPT_TILE_Y = 0, 1
+SGN_PATH_PAIRS, SGN_PATH_STAGES = 0, 1
 
 
 class SgnError(RuntimeError):
@@ -61,6 +63,7 @@ def load_library() -> ctypes.CDLL:
         "sgn_create": ([ctypes.POINTER(SgnParams), vp, ctypes.POINTER(vp)], st),
         "sgn_destroy": ([vp], st),
         "sgn_set_stream": ([vp, vp], st),
+        "sgn_set_option": ([vp, ctypes.c_int32, ctypes.c_int64], st),
         "sgn_set_bathymetry": ([vp, cvp], st),
         "sgn_init_aux": ([vp, vp], st),
         "sgn_rhs": ([vp, cvp, vp, d], st),
@@ -163,6 +166,16 @@ class Solver:
         dx, dy = ctypes.c_double(), ctypes.c_double()
         self._chk(self.lib.sgn_spacing(self.ctx, ctypes.byref(dx), ctypes.byref(dy)))
         return dx.value, dy.value
+
+    def set_option(self, option: int, value: int):
+        self._chk(self.lib.sgn_set_option(self.ctx, int(option), int(value)))
+
+    def set_step_path(self, path: str):
+        """'pairs' (two fused stage pairs per step, default) or 'stages' (four stage kernels)."""
+        self.set_option(SGN_OPT_STEP_PATH, {"pairs": SGN_PATH_PAIRS, "stages": SGN_PATH_STAGES}[path])
+
+    def set_tile_y(self, ty: int):
+        self.set_option(SGN_OPT_TILE_Y, ty)
 
     def set_bathymetry(self, b):
         self._chk(self.lib.sgn_set_bathymetry(self.ctx, self._plane(b)))

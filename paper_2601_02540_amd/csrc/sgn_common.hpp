@@ -59,6 +59,17 @@ struct CSum {
   }
 };
 
+// `true` that the compiler cannot see through (an empty asm statement that
+// claims to modify a VGPR; no instruction is emitted).  Used where a predicate
+// that is constant for one boundary type would otherwise turn a guarded phase
+// into straight-line code that the scheduler hoists across, at the price of
+// doubling the kernel's register footprint.
+__device__ __forceinline__ bool opaque_true() {
+  int one = 1;
+  asm volatile("" : "+v"(one));
+  return one != 0;
+}
+
 // Blocks are dealt to the eight XCDs of the MI355X round-robin (block b runs on
 // XCD b mod 8).  Give every XCD one contiguous range of tiles in row-major
 // order so that the halo rows shared by vertically adjacent tiles are fetched

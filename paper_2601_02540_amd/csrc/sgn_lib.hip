@@ -8,15 +8,14 @@
 
 #include "sgn.h"
 #include "sgn_reduce.hpp"
+#include "sgn_pair.hpp"
 #include "sgn_stage.hpp"
 
 namespace {
 
 thread_local std::string g_create_error;
 
-// Stage tile height used by rhs() and step().
-constexpr int STAGE_TY = 8;
-// Steps captured per graph replay.
+// Steps captured per graph replay (even, so the pair path returns to q).
 constexpr int GRAPH_STEPS = 8;
 
 struct GraphCache {
@@ -24,6 +23,8 @@ struct GraphCache {
   const void* q = nullptr;
   double dt = 0.0;
   int steps = 0;
+  int path = -1;
+  int tile_y = 0;
 };
 
 }  // namespace
@@ -46,6 +47,8 @@ struct sgn_ctx {
   int* flag = nullptr;
   int* host_flag = nullptr;
   bool b_set = false;
+  int step_path = SGN_PATH_PAIRS;
+  int tile_y = 8;
   GraphCache graphs[2];
   std::string err;
 };
@@ -86,10 +89,9 @@ int reduce_blocks(const sgn_ctx* c) { return c->p.ny < sgn::RED_MAX_BLOCKS ? c->
 // ---------------------------------------------------------------------------
 // Stage launches
 
-template <typename T, int MODE>
-hipError_t launch_stage_t(const sgn_ctx* c, hipStream_t s, const void* Y, const void* qn, void* acc, void* out,
-                          double c_acc, double c_y, double t) {
-  constexpr int TY = STAGE_TY;
+template <typename T, int MODE, int TY>
+hipError_t launch_stage_ty(const sgn_ctx* c, hipStream_t s, const void* Y, const void* qn, void* acc, void* out,
+                           double c_acc, double c_y, double t) {
   const int ntx = (c->p.nx + sgn::TILE_X - 1) / sgn::TILE_X;
   const int nty = (c->p.ny + TY - 1) / TY;
   const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
@@ -121,8 +123,69 @@ hipError_t launch_stage_t(const sgn_ctx* c, hipStream_t s, const void* Y, const 
 template <int MODE>
 hipError_t launch_stage(const sgn_ctx* c, hipStream_t s, const void* Y, const void* qn, void* acc, void* out,
                         double c_acc, double c_y, double t) {
-  if (c->p.dtype == SGN_F64) return launch_stage_t<double, MODE>(c, s, Y, qn, acc, out, c_acc, c_y, t);
-  return launch_stage_t<float, MODE>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+  if (c->p.dtype == SGN_F64) {
+    if (c->tile_y == 16) return launch_stage_ty<double, MODE, 16>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+    return launch_stage_ty<double, MODE, 8>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+  }
+  if (c->tile_y == 16) return launch_stage_ty<float, MODE, 16>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+  return launch_stage_ty<float, MODE, 8>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+}
+
+template <typename T, int PAIR, int TY>
+hipError_t launch_pair_ty(const sgn_ctx* c, hipStream_t s, const void* Yin, const void* qn, void* acc_io, void* yb,
+                          double c1_acc, double c1_y, double c2_acc, double c2_y, double t1, double t2) {
+  const int ntx = (c->p.nx + sgn::TILE_X - 1) / sgn::TILE_X;
+  const int nty = (c->p.ny + TY - 1) / TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
+  const bool src = c->p.source == SGN_SRC_MMS;
+  const T* Yp = (const T*)Yin;
+  const T* bp = (const T*)c->b;
+  const T* qp = (const T*)qn;
+  T* ap = (T*)acc_io;
+  T* yp = (T*)yb;
+#define SGN_LAUNCH(BX, BY, S)                                                                                 \
+  hipLaunchKernelGGL((sgn::pair_kernel<T, BX, BY, PAIR, S, TY>), grid, block, 0, s, c->gc, Yp, bp, qp, ap, yp, \
+                     (T)c1_acc, (T)c1_y, (T)c2_acc, (T)c2_y, t1, t2, c->flag)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (!src) {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, false);
+    else SGN_LAUNCH(1, 1, false);
+  } else {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, true);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, true);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, true);
+    else SGN_LAUNCH(1, 1, true);
+  }
+#undef SGN_LAUNCH
+  return hipGetLastError();
+}
+
+template <int PAIR>
+hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const void* qn, void* acc_io, void* yb,
+                       double c1_acc, double c1_y, double c2_acc, double c2_y, double t1, double t2) {
+  if (c->p.dtype == SGN_F64) {
+    if (c->tile_y == 16) return launch_pair_ty<double, PAIR, 16>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
+    return launch_pair_ty<double, PAIR, 8>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
+  }
+  if (c->tile_y == 16) return launch_pair_ty<float, PAIR, 16>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
+  return launch_pair_ty<float, PAIR, 8>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
+}
+
+// One RK4 step with two fused stage pairs, from state buffer `cur` into `oth`
+// (which also carries acc between the two launches).
+hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {
+  hipError_t e = launch_pair<1>(c, s, cur, nullptr, oth, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
+  if (e) return e;
+  return launch_pair<2>(c, s, c->yb, cur, oth, nullptr, dt / 3.0, dt, dt / 6.0, 0.0, t + dt / 2.0, t + dt);
+}
+
+// Two RK4 steps on the pair path: q -> acc -> q.
+hipError_t enqueue_pair_double_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, double t) {
+  hipError_t e = enqueue_pair_step(c, s, q, c->acc, dt, t);
+  if (e) return e;
+  return enqueue_pair_step(c, s, c->acc, q, dt, t + dt);
 }
 
 // One classical RK4 step in three-register form (q, acc, and two stage planes):
@@ -138,9 +201,21 @@ hipError_t enqueue_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, dou
   return launch_stage<sgn::MODE_LAST>(c, s, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
 }
 
+// Enqueues `steps` RK4 steps on the context's step path (an even count on the
+// pair path).
+hipError_t enqueue_steps(const sgn_ctx* c, hipStream_t s, void* q, double dt, int steps, double t0) {
+  hipError_t e = hipSuccess;
+  if (c->step_path == SGN_PATH_PAIRS) {
+    for (int k = 0; k + 1 < steps && e == hipSuccess; k += 2) e = enqueue_pair_double_step(c, s, q, dt, t0 + k * dt);
+  } else {
+    for (int k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(c, s, q, dt, t0 + k * dt);
+  }
+  return e;
+}
+
 sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGraphExec_t* out) {
   GraphCache& g = c->graphs[slot];
-  if (g.exec && g.q == q && g.dt == dt && g.steps == steps) {
+  if (g.exec && g.q == q && g.dt == dt && g.steps == steps && g.path == c->step_path && g.tile_y == c->tile_y) {
     *out = g.exec;
     return SGN_OK;
   }
@@ -149,8 +224,7 @@ sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGra
     g = GraphCache{};
   }
   HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t le = hipSuccess;
-  for (int k = 0; k < steps && le == hipSuccess; ++k) le = enqueue_step(c, c->cap_stream, q, dt, 0.0);
+  hipError_t le = enqueue_steps(c, c->cap_stream, q, dt, steps, 0.0);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(c->cap_stream, &graph);
   if (le != hipSuccess) {
@@ -166,6 +240,8 @@ sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGra
   g.q = q;
   g.dt = dt;
   g.steps = steps;
+  g.path = c->step_path;
+  g.tile_y = c->tile_y;
   *out = exec;
   return SGN_OK;
 }
@@ -247,6 +323,7 @@ sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
   c->p = *p;
   c->N = N;
   c->esize = p->dtype == SGN_F64 ? sizeof(double) : sizeof(float);
+  c->tile_y = p->dtype == SGN_F64 ? 8 : 16;  // measured best on MI355X at 4096^2
   c->stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
@@ -364,8 +441,11 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
   if (!std::isfinite(t0)) return fail(c, SGN_E_ARG, "t0 must be finite");
   if (nsteps == 0) return SGN_OK;
   if (c->p.source != SGN_SRC_NONE) {
-    // Stage times matter: launch directly.
-    for (int64_t s = 0; s < nsteps; ++s) HIPCHK(c, enqueue_step(c, c->stream, q, dt, t0 + (double)s * dt));
+    // Stage times matter: launch directly (pairs of steps, then a single one).
+    int64_t s = 0;
+    if (c->step_path == SGN_PATH_PAIRS)
+      for (; s + 1 < nsteps; s += 2) HIPCHK(c, enqueue_pair_double_step(c, c->stream, q, dt, t0 + (double)s * dt));
+    for (; s < nsteps; ++s) HIPCHK(c, enqueue_step(c, c->stream, q, dt, t0 + (double)s * dt));
     return SGN_OK;
   }
   int64_t left = nsteps;
@@ -374,11 +454,29 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
     if ((st = get_graph(c, 0, q, dt, GRAPH_STEPS, &ge))) return st;
     for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIPCHK(c, hipGraphLaunch(ge, c->stream));
   }
-  if (left > 0) {
+  const int small = c->step_path == SGN_PATH_PAIRS ? 2 : 1;
+  if (left >= small) {
     hipGraphExec_t g1;
-    if ((st = get_graph(c, 1, q, dt, 1, &g1))) return st;
-    for (; left > 0; --left) HIPCHK(c, hipGraphLaunch(g1, c->stream));
+    if ((st = get_graph(c, 1, q, dt, small, &g1))) return st;
+    for (; left >= small; left -= small) HIPCHK(c, hipGraphLaunch(g1, c->stream));
   }
+  // An odd final step on the pair path runs as four single-stage kernels in place.
+  if (left > 0) HIPCHK(c, enqueue_step(c, c->stream, q, dt, 0.0));
+  return SGN_OK;
+}
+
+sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
+  if (!c) return SGN_E_ARG;
+  if (option == SGN_OPT_STEP_PATH) {
+    if (value != SGN_PATH_PAIRS && value != SGN_PATH_STAGES) return fail(c, SGN_E_ARG, "unknown step path");
+    c->step_path = (int)value;
+  } else if (option == SGN_OPT_TILE_Y) {
+    if (value != 8 && value != 16) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
+    c->tile_y = (int)value;
+  } else {
+    return fail(c, SGN_E_ARG, "unknown option");
+  }
+  destroy_graphs(c);
   return SGN_OK;
 }
 
@@ -444,23 +542,38 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if (st) return st;
   if (!q || !ms) return fail(c, SGN_E_ARG, "q or ms is NULL");
   if (!(std::isfinite(dt) && dt > 0.0) || nsteps <= 0) return fail(c, SGN_E_ARG, "dt must be > 0 and nsteps > 0");
+  const bool pairs = c->step_path == SGN_PATH_PAIRS;
+  if (pairs && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
+  const int nk = pairs ? 4 : 4;         // launches recorded per profiled unit
   hipEvent_t ev[5];
   for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventCreate(&ev[k]));
   double acc_ms[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
-  for (int64_t s = 0; s < nsteps && e == hipSuccess; ++s) {
-    const double t = (double)s * dt;
+  const int64_t units = pairs ? nsteps / 2 : nsteps;
+  for (int64_t u = 0; u < units && e == hipSuccess; ++u) {
+    const double t = (double)u * (pairs ? 2.0 : 1.0) * dt;
     e = hipEventRecord(ev[0], c->stream);
-    if (!e) e = launch_stage<sgn::MODE_FIRST>(c, c->stream, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t);
-    if (!e) e = hipEventRecord(ev[1], c->stream);
-    if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->ya, q, c->acc, c->yb, dt / 3.0, dt / 2.0, t + dt / 2.0);
-    if (!e) e = hipEventRecord(ev[2], c->stream);
-    if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->yb, q, c->acc, c->ya, dt / 3.0, dt, t + dt / 2.0);
-    if (!e) e = hipEventRecord(ev[3], c->stream);
-    if (!e) e = launch_stage<sgn::MODE_LAST>(c, c->stream, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
+    if (pairs) {
+      // pair 1 and pair 2 of two consecutive steps (q -> acc -> q)
+      if (!e) e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
+      if (!e) e = hipEventRecord(ev[1], c->stream);
+      if (!e) e = launch_pair<2>(c, c->stream, c->yb, q, c->acc, nullptr, dt / 3.0, dt, dt / 6.0, 0.0, t + dt / 2.0, t + dt);
+      if (!e) e = hipEventRecord(ev[2], c->stream);
+      if (!e) e = launch_pair<1>(c, c->stream, c->acc, nullptr, q, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t + dt, t + 1.5 * dt);
+      if (!e) e = hipEventRecord(ev[3], c->stream);
+      if (!e) e = launch_pair<2>(c, c->stream, c->yb, c->acc, q, nullptr, dt / 3.0, dt, dt / 6.0, 0.0, t + 1.5 * dt, t + 2.0 * dt);
+    } else {
+      if (!e) e = launch_stage<sgn::MODE_FIRST>(c, c->stream, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t);
+      if (!e) e = hipEventRecord(ev[1], c->stream);
+      if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->ya, q, c->acc, c->yb, dt / 3.0, dt / 2.0, t + dt / 2.0);
+      if (!e) e = hipEventRecord(ev[2], c->stream);
+      if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->yb, q, c->acc, c->ya, dt / 3.0, dt, t + dt / 2.0);
+      if (!e) e = hipEventRecord(ev[3], c->stream);
+      if (!e) e = launch_stage<sgn::MODE_LAST>(c, c->stream, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
+    }
     if (!e) e = hipEventRecord(ev[4], c->stream);
     if (!e) e = hipEventSynchronize(ev[4]);
-    for (int k = 0; k < 4 && !e; ++k) {
+    for (int k = 0; k < nk && !e; ++k) {
       float m = 0.f;
       e = hipEventElapsedTime(&m, ev[k], ev[k + 1]);
       acc_ms[k] += m;
@@ -468,7 +581,15 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   }
   for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
   if (e != hipSuccess) return hip_fail(c, e, "profiled step");
-  for (int k = 0; k < 4; ++k) ms[k] = acc_ms[k] / (double)nsteps;
+  if (pairs) {
+    // ms[0] = pair 1, ms[1] = pair 2 (means over both steps of each unit)
+    ms[0] = (acc_ms[0] + acc_ms[2]) / (2.0 * (double)units);
+    ms[1] = (acc_ms[1] + acc_ms[3]) / (2.0 * (double)units);
+    ms[2] = 0.0;
+    ms[3] = 0.0;
+  } else {
+    for (int k = 0; k < 4; ++k) ms[k] = acc_ms[k] / (double)units;
+  }
   return sync_results(c, 0);
 }
 

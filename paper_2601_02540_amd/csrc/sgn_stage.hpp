@@ -165,16 +165,14 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const GridConst gc
     int gi = i0 - 1 + cc;
     int gj = j0 - 1 + rr;
     if (BCX == BC_PERIODIC) {
-      gi = gi < 0 ? gi + nx : gi;
-      gi = gi >= nx ? gi - nx : gi;
-      gi = gi >= nx ? gi % nx : gi;
+      if (gi < 0) gi += nx;
+      while (gi >= nx) gi -= nx;
     } else {
       gi = gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi);
     }
     if (BCY == BC_PERIODIC) {
-      gj = gj < 0 ? gj + ny : gj;
-      gj = gj >= ny ? gj - ny : gj;
-      gj = gj >= ny ? gj % ny : gj;
+      if (gj < 0) gj += ny;
+      while (gj >= ny) gj -= ny;
     } else {
       gj = gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj);
     }

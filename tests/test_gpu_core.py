@@ -241,3 +241,59 @@ def test_step_fp32_bounded_by_oracle_fp32():
     m, e = s.mass_energy(qd)
     mo, eo = oracle.mass_energy(g, got, p.b.astype(np.float32).astype(np.float64))
     assert math.isclose(m, mo, rel_tol=1e-12) and math.isclose(e, eo, rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Step paths (two fused stage pairs per step, or four stage kernels) and tile heights
+
+@pytest.mark.parametrize("shape", [(13, 11), (150, 37), (257, 70), (64, 64)])
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
+def test_step_paths_and_tiles(shape, bcs):
+    nx, ny = shape
+    g = W.Grid(nx, ny, -1.0, 2.0, 0.5, 2.0, bcs[0], bcs[1], 9.81, 500.0)
+    q, b = W.random_state(g, 3 * nx + ny, b_scale=0.05)
+    q[1:4] *= 0.1
+    dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
+    ref3 = oracle.rk4(g, q, b, dt, 3)
+    for path in ("pairs", "stages"):
+        for ty in (8, 16):
+            s = solver(g)
+            s.set_step_path(path)
+            s.set_tile_y(ty)
+            s.set_bathymetry(dev(b))
+            qd = dev(q)
+            s.step(qd, dt, 3)  # a double step then an odd single step on the pair path
+            err = field_rel_err(host(qd), ref3, STATE_FLOORS)
+            assert np.all(err <= F64_TOL), (path, ty, err)
+
+
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_step_paths_mms_source(bc):
+    """Stage times reach the source correctly on both paths (direct launches)."""
+    g = W.mms_grid(40, bc)
+    p = W.mms_initial(g)
+    q0 = oracle.init_aux(g, p.q0, p.b)
+    dt = oracle.cfl_dt(g, q0, 0.5)
+    ref = oracle.rk4(g, q0, p.b, dt, 5, 0.1, 1)
+    for path in ("pairs", "stages"):
+        s = solver(g, source=1)
+        s.set_step_path(path)
+        s.set_bathymetry(dev(p.b))
+        qd = dev(q0)
+        s.step(qd, dt, 5, t0=0.1)
+        err = field_rel_err(host(qd), ref, STATE_FLOORS)
+        assert np.all(err <= F64_TOL), (path, err)
+
+
+def test_profile_stages_both_paths():
+    p = W.gaussian_bump_periodic(256, seed=2)
+    q0 = oracle.init_aux(p.grid, p.q0, p.b)
+    for path, nk in (("pairs", 2), ("stages", 4)):
+        s = solver(p.grid)
+        s.set_step_path(path)
+        s.set_bathymetry(dev(p.b))
+        qd = dev(q0)
+        ms = s.profile_stages(qd, 0.01, 4)
+        assert all(m > 0 for m in ms[:nk]) and all(m == 0 for m in ms[nk:])
+        ref = oracle.rk4(p.grid, q0, p.b, 0.01, 4)
+        assert np.all(field_rel_err(host(qd), ref, STATE_FLOORS) <= F64_TOL)
