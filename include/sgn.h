@@ -161,6 +161,53 @@ sgn_status sgn_check(sgn_ctx* ctx);
 /* Grid spacing used by the context (host doubles). */
 sgn_status sgn_spacing(const sgn_ctx* ctx, double* dx, double* dy);
 
+/* ------------------------------------------------------------------------
+ * Ensembles: many independent problems advanced together.
+ *
+ * Every instance has its own sgn_params (grid size, domain, boundary types, g,
+ * lambda; all instances share one dtype; no source terms) and its own time
+ * step.  The tiles of all instances form one work list; each RK4 step is two
+ * launches of one persistent kernel over the whole list (the stage-pair
+ * scheme of SGN_PATH_PAIRS, boundary variant chosen per instance), and steps
+ * are replayed from a captured HIP graph.  Results are identical to advancing
+ * each instance alone with sgn_step on the pair path with the same tile height.
+ *
+ * The caller owns the states (n device pointers, each 5 planes of that
+ * instance's ny*nx values in the batch dtype) and passes them with
+ * sgn_batch_set_states; the batch owns packed copies of the bathymetries, the
+ * scratch states and per-instance health flags.  Synchronization, errors and
+ * threading follow the single-problem rules above.
+ * ------------------------------------------------------------------------ */
+typedef struct sgn_batch sgn_batch;
+
+sgn_status sgn_batch_create(int32_t n, const sgn_params* params, void* stream, sgn_batch** out);
+sgn_status sgn_batch_destroy(sgn_batch* batch);
+/* Copy instance i's bathymetry (device plane of its ny*nx values). */
+sgn_status sgn_batch_set_bathymetry(sgn_batch* batch, int32_t i, const void* b);
+/* Register the n state pointers (q[i] device, caller-owned, not copied). */
+sgn_status sgn_batch_set_states(sgn_batch* batch, void* const* q);
+/* eq. (initialization) on every state in place. */
+sgn_status sgn_batch_init_aux(sgn_batch* batch);
+/* Advance every instance by nsteps RK4 steps; dt is a host array of n steps. */
+sgn_status sgn_batch_step(sgn_batch* batch, const double* dt, int64_t nsteps);
+/* Per-instance totals into host arrays of n doubles (either may be NULL).  Synchronizes. */
+sgn_status sgn_batch_mass_energy(sgn_batch* batch, double* mass, double* energy);
+/* Per-instance CFL steps (rule of sgn_cfl_dt) into a host array of n doubles.  Synchronizes. */
+sgn_status sgn_batch_cfl_dt(sgn_batch* batch, double cfl, double* dt);
+/* Tile height (8 or 16) and persistent workgroups per compute unit (1..16). */
+sgn_status sgn_batch_set_tiling(sgn_batch* batch, int32_t tile_y, int32_t blocks_per_cu);
+/* Time every (tile height, workgroups per CU) candidate on one step from the
+ * registered states into scratch (the states are read, never written), keep
+ * the fastest and report it (any output may be NULL; ms = time of one step).
+ * Synchronizes. */
+sgn_status sgn_batch_autotune(sgn_batch* batch, const double* dt, int32_t* tile_y, int32_t* blocks_per_cu,
+                              double* ms);
+/* Synchronize; report (and clear) health flags; *first_bad = first failing instance or -1. */
+sgn_status sgn_batch_check(sgn_batch* batch, int32_t* first_bad);
+/* Sum of nx*ny over the instances. */
+sgn_status sgn_batch_total_nodes(const sgn_batch* batch, int64_t* nodes);
+const char* sgn_batch_last_error(const sgn_batch* batch);
+
 /* Message of the last failed call on ctx (or of the last failed sgn_create when ctx is NULL). */
 const char* sgn_last_error(const sgn_ctx* ctx);
 

@@ -77,6 +77,19 @@ def load_library() -> ctypes.CDLL:
         "sgn_profile_stages": ([vp, vp, d, ctypes.c_int64, dp], st),
         "sgn_spacing": ([vp, dp, dp], st),
         "sgn_last_error": ([vp], ctypes.c_char_p),
+        "sgn_batch_create": ([ctypes.c_int32, ctypes.POINTER(SgnParams), vp, ctypes.POINTER(vp)], st),
+        "sgn_batch_destroy": ([vp], st),
+        "sgn_batch_set_bathymetry": ([vp, ctypes.c_int32, cvp], st),
+        "sgn_batch_set_states": ([vp, ctypes.POINTER(vp)], st),
+        "sgn_batch_init_aux": ([vp], st),
+        "sgn_batch_step": ([vp, dp, ctypes.c_int64], st),
+        "sgn_batch_mass_energy": ([vp, dp, dp], st),
+        "sgn_batch_cfl_dt": ([vp, d, dp], st),
+        "sgn_batch_set_tiling": ([vp, ctypes.c_int32, ctypes.c_int32], st),
+        "sgn_batch_autotune": ([vp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp], st),
+        "sgn_batch_check": ([vp, ctypes.POINTER(ctypes.c_int32)], st),
+        "sgn_batch_total_nodes": ([vp, ctypes.POINTER(ctypes.c_int64)], st),
+        "sgn_batch_last_error": ([vp], ctypes.c_char_p),
         "sgn_status_string": ([ctypes.c_int32], ctypes.c_char_p),
     }
     for name, (args, res) in sigs.items():
@@ -228,3 +241,100 @@ class Solver:
 
     def check(self):
         self._chk(self.lib.sgn_check(self.ctx))
+
+
+class Batch:
+    """An ensemble of independent problems (C-ABI sgn_batch_*).
+
+    ``grids`` is a list of grid objects (see :class:`Solver`); all instances share
+    ``dtype``.  States are caller-owned tensors registered with :meth:`set_states`.
+    """
+
+    def __init__(self, grids, dtype=None):
+        torch = _torch()
+        _require_gpu()
+        self.lib = load_library()
+        self.grids = list(grids)
+        self.n = len(self.grids)
+        self.dtype = torch.float64 if dtype is None else dtype
+        code = SGN_F64 if self.dtype == torch.float64 else SGN_F32
+        arr = (SgnParams * self.n)(*[SgnParams(g.nx, g.ny, g.xmin, g.xmax, g.ymin, g.ymax, g.bc_x, g.bc_y, g.g,
+                                               g.lam, code, SGN_SRC_NONE) for g in self.grids])
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        s = self.lib.sgn_batch_create(self.n, arr, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if s != 0:
+            raise SgnError(s, self.lib.sgn_batch_last_error(None).decode())
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sgn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, s):
+        if s != 0:
+            raise SgnError(s, self.lib.sgn_batch_last_error(self.h).decode())
+
+    def _dbl(self, vals):
+        return (ctypes.c_double * self.n)(*[float(v) for v in vals])
+
+    def set_bathymetry(self, i: int, b):
+        g = self.grids[i]
+        if tuple(b.shape) != (g.ny, g.nx) or b.dtype != self.dtype or not b.is_contiguous():
+            raise ValueError(f"bathymetry {i} must be a contiguous {self.dtype} tensor of shape {(g.ny, g.nx)}")
+        self._chk(self.lib.sgn_batch_set_bathymetry(self.h, i, ctypes.c_void_p(b.data_ptr())))
+        self._keep.append(b)
+
+    def set_states(self, qs):
+        for i, (q, g) in enumerate(zip(qs, self.grids)):
+            if tuple(q.shape) != (5, g.ny, g.nx) or q.dtype != self.dtype or not q.is_contiguous():
+                raise ValueError(f"state {i} must be a contiguous {self.dtype} tensor of shape {(5, g.ny, g.nx)}")
+        ptrs = (ctypes.c_void_p * self.n)(*[q.data_ptr() for q in qs])
+        self._chk(self.lib.sgn_batch_set_states(self.h, ptrs))
+        self.states = list(qs)
+
+    def init_aux(self):
+        self._chk(self.lib.sgn_batch_init_aux(self.h))
+
+    def step(self, dt, nsteps: int = 1):
+        self._chk(self.lib.sgn_batch_step(self.h, self._dbl(dt), int(nsteps)))
+
+    def mass_energy(self):
+        m = (ctypes.c_double * self.n)()
+        e = (ctypes.c_double * self.n)()
+        self._chk(self.lib.sgn_batch_mass_energy(self.h, m, e))
+        return list(m), list(e)
+
+    def cfl_dt(self, cfl: float = 0.5):
+        out = (ctypes.c_double * self.n)()
+        self._chk(self.lib.sgn_batch_cfl_dt(self.h, float(cfl), out))
+        return list(out)
+
+    def set_tiling(self, tile_y: int, blocks_per_cu: int):
+        self._chk(self.lib.sgn_batch_set_tiling(self.h, int(tile_y), int(blocks_per_cu)))
+
+    def autotune(self, dt):
+        ty, bpc = ctypes.c_int32(), ctypes.c_int32()
+        ms = ctypes.c_double()
+        self._chk(self.lib.sgn_batch_autotune(self.h, self._dbl(dt), ctypes.byref(ty), ctypes.byref(bpc),
+                                              ctypes.byref(ms)))
+        return ty.value, bpc.value, ms.value
+
+    def check(self):
+        bad = ctypes.c_int32(-1)
+        self._chk(self.lib.sgn_batch_check(self.h, ctypes.byref(bad)))
+        return bad.value
+
+    def total_nodes(self) -> int:
+        n = ctypes.c_int64()
+        self._chk(self.lib.sgn_batch_total_nodes(self.h, ctypes.byref(n)))
+        return n.value

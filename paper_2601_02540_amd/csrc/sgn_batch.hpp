@@ -1,0 +1,74 @@
+// sgn_batch.hpp -- an ensemble of independent problems in one persistent launch
+// per stage pair.
+//
+// Every instance has its own grid size, boundary types, spacing, g, lambda and
+// time step.  The tiles of all instances form one work list (instance-major,
+// row-major tiles within an instance).  A persistent grid of workgroups walks
+// the list: the list is cut into eight contiguous ranges, one per XCD, so tiles
+// of the same instance (and their shared halo rows) stay in one L2.  Each work
+// item runs the same pair_tile code as the single-problem kernel, with the
+// boundary variant chosen per instance at run time (uniform per workgroup).
+#pragma once
+
+#include "sgn_pair.hpp"
+
+namespace sgn {
+
+struct InstDesc {
+  GridConst gc;
+  double dt;
+  int tile_base;  // first work item of this instance
+  int ntx, nty;   // tiles per axis
+  int pad;
+  void* q;        // caller's state
+  void* acc;      // scratch state (second buffer of the ping-pong)
+  void* yb;       // scratch stage plane set
+  const void* b;  // bathymetry copy
+};
+
+template <typename T, int PAIR, int TY, int BCX, int BCY>
+__device__ __forceinline__ void batch_tile(PairSmem<T, TY>& s, const InstDesc& d, int i0, int j0, int parity,
+                                           int* flag) {
+  T* q = (T*)d.q;
+  T* acc = (T*)d.acc;
+  T* cur = parity ? acc : q;
+  T* oth = parity ? q : acc;
+  const T* b = (const T*)d.b;
+  T* yb = (T*)d.yb;
+  const double dt = d.dt;
+  if (PAIR == 1)
+    pair_tile<T, BCX, BCY, 1, false, TY>(s, d.gc, i0, j0, cur, b, nullptr, oth, yb, T(dt / 6.0), T(dt / 2.0),
+                                         T(dt / 3.0), T(dt / 2.0), 0.0, 0.0, flag);
+  else
+    pair_tile<T, BCX, BCY, 2, false, TY>(s, d.gc, i0, j0, yb, b, cur, oth, nullptr, T(dt / 3.0), T(dt),
+                                         T(dt / 6.0), T(0.0), 0.0, 0.0, flag);
+}
+
+// parity 0: state in q, written to acc; parity 1: state in acc, written to q.
+template <typename T, int PAIR, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void batch_pair_kernel(const InstDesc* __restrict__ desc,
+                                                                   const int* __restrict__ work_inst, int nwork,
+                                                                   int parity, int* __restrict__ flags) {
+  __shared__ PairSmem<T, TY> s;
+  const int xcd = blockIdx.x & 7;
+  const int k = blockIdx.x >> 3;
+  const int blocks_per_xcd = gridDim.x >> 3;  // the grid is a multiple of 8
+  const int start = (int)((long long)nwork * xcd / 8);
+  const int end = (int)((long long)nwork * (xcd + 1) / 8);
+  for (int w = start + k; w < end; w += blocks_per_xcd) {
+    const int inst = work_inst[w];
+    const InstDesc d = desc[inst];
+    const int t = w - d.tile_base;
+    const int i0 = (t % d.ntx) * TILE_X;
+    const int j0 = (t / d.ntx) * TY;
+    switch (d.gc.bc_x * 2 + d.gc.bc_y) {
+      case 0: batch_tile<T, PAIR, TY, 0, 0>(s, d, i0, j0, parity, flags + inst); break;
+      case 1: batch_tile<T, PAIR, TY, 0, 1>(s, d, i0, j0, parity, flags + inst); break;
+      case 2: batch_tile<T, PAIR, TY, 1, 0>(s, d, i0, j0, parity, flags + inst); break;
+      default: batch_tile<T, PAIR, TY, 1, 1>(s, d, i0, j0, parity, flags + inst); break;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace sgn

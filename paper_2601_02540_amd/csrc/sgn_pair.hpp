@@ -97,29 +97,24 @@ __device__ __forceinline__ Rates<T> pair_eval(const PairSmem<T, TY>& s, int r, i
   return k;
 }
 
+// One tile (origin i0, j0) of a stage pair, executed by a whole workgroup.
 // PAIR = 1: Yin = q (state), writes acc_io = acc and yb_out = Yb.
 // PAIR = 2: Yin = Yb, qn = q (state), acc_io holds acc on entry and q_new on exit.
+// The caller synchronizes the workgroup before reusing `s` for another tile.
 template <typename T, int BCX, int BCY, int PAIR, bool SRC, int TY>
-__global__ __launch_bounds__(STAGE_THREADS) void pair_kernel(const GridConst gc, const T* __restrict__ Yin,
-                                                             const T* __restrict__ bplane, const T* __restrict__ qn,
-                                                             T* acc_io, T* __restrict__ yb_out, T c1_acc, T c1_y,
-                                                             T c2_acc, T c2_y, double t1, double t2,
-                                                             int* __restrict__ flag) {
+__device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& gc, int i0, int j0,
+                                          const T* __restrict__ Yin, const T* __restrict__ bplane,
+                                          const T* __restrict__ qn, T* acc_io, T* __restrict__ yb_out, T c1_acc,
+                                          T c1_y, T c2_acc, T c2_y, double t1, double t2, int* __restrict__ flag) {
   static_assert(TY % THREAD_ROWS == 0, "tile height must be a multiple of 4");
   constexpr int RPT = TY / THREAD_ROWS;
   constexpr int W2 = TILE_X + 4;
   constexpr int REGION = (TY + 4) * W2;
   constexpr int RING = 2 * (TILE_X + 2) + 2 * TY;
   static_assert(RING <= STAGE_THREADS, "ring must fit one pass");
-  __shared__ PairSmem<T, TY> s;
 
   const int nx = gc.nx, ny = gc.ny;
   const size_t N = (size_t)nx * (size_t)ny;
-  const int ntx = (nx + TILE_X - 1) / TILE_X;
-  const int nty = (ny + TY - 1) / TY;
-  const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  const int i0 = (tile % ntx) * TILE_X;
-  const int j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
   const int tx = tid & (TILE_X - 1);
   const int ty = tid >> 6;
@@ -288,6 +283,20 @@ __global__ __launch_bounds__(STAGE_THREADS) void pair_kernel(const GridConst gc,
     }
   }
   if (PAIR == 2 && health) atomicOr(flag, health);
+}
+
+template <typename T, int BCX, int BCY, int PAIR, bool SRC, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void pair_kernel(const GridConst gc, const T* __restrict__ Yin,
+                                                             const T* __restrict__ bplane, const T* __restrict__ qn,
+                                                             T* acc_io, T* __restrict__ yb_out, T c1_acc, T c1_y,
+                                                             T c2_acc, T c2_y, double t1, double t2,
+                                                             int* __restrict__ flag) {
+  __shared__ PairSmem<T, TY> s;
+  const int ntx = (gc.nx + TILE_X - 1) / TILE_X;
+  const int nty = (gc.ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  pair_tile<T, BCX, BCY, PAIR, SRC, TY>(s, gc, (tile % ntx) * TILE_X, (tile / ntx) * TY, Yin, bplane, qn, acc_io,
+                                        yb_out, c1_acc, c1_y, c2_acc, c2_y, t1, t2, flag);
 }
 
 }  // namespace sgn

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(RED_THREADS) void totals_partial(const GridConst gc
 }
 
 // One block: combines nparts partials in block order; result[0..1] = totals.
-__global__ __launch_bounds__(RED_THREADS) void totals_final(const double* __restrict__ partials, int nparts,
+static __global__ __launch_bounds__(RED_THREADS) void totals_final(const double* __restrict__ partials, int nparts,
                                                             double* __restrict__ result) {
   CSum a[2];
   a[0].init();
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(RED_THREADS) void speed_partial(const GridConst gc,
   }
 }
 
-__global__ __launch_bounds__(RED_THREADS) void speed_final(const double* __restrict__ partials, int nparts,
+static __global__ __launch_bounds__(RED_THREADS) void speed_final(const double* __restrict__ partials, int nparts,
                                                            double* __restrict__ result) {
   double m = 0.0;
   for (int p = threadIdx.x; p < nparts; p += RED_THREADS) m = (partials[p] > m || partials[p] != partials[p]) ? partials[p] : m;
