@@ -70,10 +70,12 @@ def _load():
         lib.orc_cfl_dt.restype = d
         lib.orc_mms_fields.argtypes = [gp, d, dp, dp]
         lib.orc_mms_source.argtypes = [gp, d, dp]
-        if hasattr(lib, "orc_rhs_vjp"):
-            lib.orc_rhs_vjp.argtypes = [gp, dp, dp, dp, dp, dp]
-        if hasattr(lib, "orc_rk4_vjp"):
-            lib.orc_rk4_vjp.argtypes = [gp, dp, dp, d, dp, dp]
+        lib.orc_rhs_vjp.argtypes = [gp, dp, dp, dp, dp, dp]
+        lib.orc_rk4_vjp.argtypes = [gp, dp, dp, d, dp, dp]
+        lib.orc_rk4_jvp.argtypes = [gp, dp, dp, d, dp, dp, dp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.orc_gauge_loss.argtypes = [gp, dp, dp, d, ctypes.c_int64, i64p, ctypes.c_int, dp, dp, dp, dp, dp]
+        lib.orc_gauge_loss_grad.argtypes = [gp, dp, dp, d, ctypes.c_int64, i64p, ctypes.c_int, dp, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -241,3 +243,49 @@ def rk4_vjp(grid, q, b, dt: float, qbar):
     bb = np.zeros_like(b)
     _load().orc_rk4_vjp(ctypes.byref(_grid(grid)), _dp(q), _dp(b), dt, _dp(qb), _dp(bb))
     return qb, bb
+
+
+def rk4_jvp(grid, q, b, dt: float, dq, db=None):
+    """Directional derivative of one RK4 step along (dq, db) by the complex step."""
+    q = _state(q, grid)
+    b = _plane(b, grid)
+    dq = _state(dq, grid)
+    out = np.empty_like(q)
+    dbp = _dp(_plane(db, grid)) if db is not None else None
+    _load().orc_rk4_jvp(ctypes.byref(_grid(grid)), _dp(q), _dp(b), dt, _dp(dq), dbp, _dp(out))
+    return out
+
+
+def _gauges(gidx):
+    g = np.ascontiguousarray(gidx, dtype=np.int64)
+    return g, g.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+def gauge_loss(grid, zeta0, b, dt, nsteps, gauge_nodes, target, dzeta0=None, db=None):
+    """(L, dL along (dzeta0, db)) by the complex step; gauge_nodes are row-major node indices."""
+    zeta0 = _plane(zeta0, grid)
+    b = _plane(b, grid)
+    g, gp = _gauges(gauge_nodes)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    assert target.shape == (nsteps, g.size)
+    L, dL = ctypes.c_double(), ctypes.c_double()
+    dz = _dp(_plane(dzeta0, grid)) if dzeta0 is not None else None
+    dbp = _dp(_plane(db, grid)) if db is not None else None
+    _load().orc_gauge_loss(ctypes.byref(_grid(grid)), _dp(zeta0), _dp(b), dt, nsteps, gp, g.size, _dp(target),
+                           dz, dbp, ctypes.byref(L), ctypes.byref(dL))
+    return L.value, dL.value
+
+
+def gauge_loss_grad(grid, zeta0, b, dt, nsteps, gauge_nodes, target):
+    """(L, dL/dzeta0, dL/db) by the discrete adjoint."""
+    zeta0 = _plane(zeta0, grid)
+    b = _plane(b, grid)
+    g, gp = _gauges(gauge_nodes)
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    assert target.shape == (nsteps, g.size)
+    L = ctypes.c_double()
+    gz = np.zeros_like(zeta0)
+    gb = np.zeros_like(b)
+    _load().orc_gauge_loss_grad(ctypes.byref(_grid(grid)), _dp(zeta0), _dp(b), dt, nsteps, gp, g.size,
+                                _dp(target), ctypes.byref(L), _dp(gz), _dp(gb))
+    return L.value, gz, gb

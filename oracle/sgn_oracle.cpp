@@ -424,6 +424,261 @@ void init_aux_impl(const Ops& o, T* q, const T* b) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Discrete adjoint (discretize, then differentiate): (q_bar, b_bar) += J^T a
+// for the Jacobian J of the right-hand side with respect to (q, b).  Written
+// term by term against rhs_impl: a term  c * X * D(Y)  of a rate with
+// cotangent abar contributes  X_bar += c abar D(Y)  and  Y_bar += D^T(c abar X),
+// and every pointwise product is then chained back to h, u, v, w, eta, b.
+void rhs_vjp_impl(const orc_grid& gr, const Ops& o, const double* q, const double* b, const double* a,
+                  double* qbar, double* bbar) {
+  const size_t N = o.N;
+  const double* h = q;
+  const double* u = q + N;
+  const double* v = q + 2 * N;
+  const double* w = q + 3 * N;
+  const double* eta = q + 4 * N;
+  const double g = gr.g, lam = gr.lambda;
+  using vec = std::vector<double>;
+
+  // forward intermediates (as in rhs_impl)
+  vec H(N), hH(N), u2(N), v2(N), hu(N), hv(N), huv(N), uv(N), e2h(N), huw(N), hvw(N), uw(N), vw(N), hw(N), r(N), r2(N);
+  for (size_t k = 0; k < N; ++k) {
+    H[k] = h[k] + b[k];
+    hH[k] = h[k] * H[k];
+    u2[k] = u[k] * u[k];
+    v2[k] = v[k] * v[k];
+    hu[k] = h[k] * u[k];
+    hv[k] = h[k] * v[k];
+    huv[k] = h[k] * u[k] * v[k];
+    uv[k] = u[k] * v[k];
+    e2h[k] = eta[k] * eta[k] / h[k];
+    huw[k] = h[k] * u[k] * w[k];
+    hvw[k] = h[k] * v[k] * w[k];
+    uw[k] = u[k] * w[k];
+    vw[k] = v[k] * w[k];
+    hw[k] = h[k] * w[k];
+    r[k] = eta[k] / h[k];
+    r2[k] = (eta[k] * eta[k]) / (h[k] * h[k]);
+  }
+  auto Dx = [&](const double* f) { vec out(N); apply_dx(o, f, out.data()); return out; };
+  auto Dy = [&](const double* f) { vec out(N); apply_dy(o, f, out.data()); return out; };
+  const vec Dxh = Dx(h), Dxu = Dx(u), Dxv = Dx(v), Dxw = Dx(w), Dxeta = Dx(eta), Dxb = Dx(b);
+  const vec Dyh = Dy(h), Dyu = Dy(u), Dyv = Dy(v), Dyw = Dy(w), Dyeta = Dy(eta), Dyb = Dy(b);
+  const vec DxhH = Dx(hH.data()), Dxu2 = Dx(u2.data()), Dxhu = Dx(hu.data()), Dxhuv = Dx(huv.data()),
+            Dxe2h = Dx(e2h.data()), Dxhuw = Dx(huw.data());
+  const vec DyhH = Dy(hH.data()), Dyv2 = Dy(v2.data()), Dyhv = Dy(hv.data()), Dyhuv = Dy(huv.data()),
+            Dye2h = Dy(e2h.data()), Dyhvw = Dy(hvw.data());
+
+  // the bracketed sums A (h u_t + A = 0), B (h v_t + B = 0), C (h w_t + C = lam (1 - r))
+  vec A(N), B(N), C(N);
+  for (size_t k = 0; k < N; ++k) {
+    A[k] = g * DxhH[k] - g * H[k] * Dxh[k] + 0.5 * h[k] * Dxu2[k] - 0.5 * u2[k] * Dxh[k] + 0.5 * u[k] * Dxhu[k] -
+           0.5 * hu[k] * Dxu[k] + 0.5 * Dyhuv[k] - 0.5 * uv[k] * Dyh[k] + 0.5 * hv[k] * Dyu[k] -
+           0.5 * hu[k] * Dyv[k] + lam / 6 * r2[k] * Dxh[k] + lam / 3 * Dxeta[k] - lam / 3 * r[k] * Dxeta[k] -
+           lam / 6 * Dxe2h[k] + lam / 2 * (1 - r[k]) * Dxb[k];
+    B[k] = g * DyhH[k] - g * H[k] * Dyh[k] + 0.5 * h[k] * Dyv2[k] - 0.5 * v2[k] * Dyh[k] + 0.5 * v[k] * Dyhv[k] -
+           0.5 * hv[k] * Dyv[k] + 0.5 * Dxhuv[k] - 0.5 * uv[k] * Dxh[k] + 0.5 * hu[k] * Dxv[k] -
+           0.5 * hv[k] * Dxu[k] + lam / 6 * r2[k] * Dyh[k] + lam / 3 * Dyeta[k] - lam / 3 * r[k] * Dyeta[k] -
+           lam / 6 * Dye2h[k] + lam / 2 * (1 - r[k]) * Dyb[k];
+    C[k] = 0.5 * Dxhuw[k] + 0.5 * hu[k] * Dxw[k] - 0.5 * uw[k] * Dxh[k] - 0.5 * hw[k] * Dxu[k] +
+           0.5 * Dyhvw[k] + 0.5 * hv[k] * Dyw[k] - 0.5 * vw[k] * Dyh[k] - 0.5 * hw[k] * Dyv[k];
+  }
+
+  // cotangents of the rates
+  const double* ah = a;
+  const double* au = a + N;
+  const double* av = a + 2 * N;
+  const double* aw = a + 3 * N;
+  const double* aeta = a + 4 * N;
+  vec hb(N, 0), ub(N, 0), vb(N, 0), wb(N, 0), etab(N, 0), bb(N, 0);
+  vec Hb(N, 0), hHb(N, 0), u2b(N, 0), v2b(N, 0), hub(N, 0), hvb(N, 0), huvb(N, 0), uvb(N, 0), e2hb(N, 0),
+      huwb(N, 0), hvwb(N, 0), uwb(N, 0), vwb(N, 0), hwb(N, 0), rb(N, 0), r2b(N, 0);
+  // seeds of A, B, C: u_t = -A/h, v_t = -B/h, w_t = (lam (1 - r) - C)/h
+  vec Ab(N), Bb(N), Cb(N);
+  for (size_t k = 0; k < N; ++k) {
+    Ab[k] = -au[k] / h[k];
+    Bb[k] = -av[k] / h[k];
+    Cb[k] = -aw[k] / h[k];
+    hb[k] += au[k] * A[k] / (h[k] * h[k]) + av[k] * B[k] / (h[k] * h[k]) -
+             aw[k] * (lam * (1 - r[k]) - C[k]) / (h[k] * h[k]);
+    rb[k] += -lam * aw[k] / h[k];
+  }
+  // term c * X * D(Y): X_bar += c abar DY ; Y_bar += D^T(c abar X)   (X == nullptr means 1)
+  vec tmp(N);
+  auto term = [&](double c, const vec& abar, const vec* X, vec* Xb, const vec& DY, vec& Yb, bool xdir) {
+    for (size_t k = 0; k < N; ++k) {
+      if (Xb) (*Xb)[k] += c * abar[k] * DY[k];
+      tmp[k] = c * abar[k] * (X ? (*X)[k] : 1.0);
+    }
+    if (xdir)
+      add_dxT(o, tmp.data(), Yb.data());
+    else
+      add_dyT(o, tmp.data(), Yb.data());
+  };
+  const vec hv_(h, h + N), uv_(u, u + N), vv_(v, v + N), wv_(w, w + N), etav_(eta, eta + N);
+  vec omr(N), ones(N, 1.0);
+  for (size_t k = 0; k < N; ++k) omr[k] = 1 - r[k];
+  vec omrb(N, 0);
+
+  // A
+  term(g, Ab, nullptr, nullptr, DxhH, hHb, true);
+  term(-g, Ab, &H, &Hb, Dxh, hb, true);
+  term(0.5, Ab, &hv_, &hb, Dxu2, u2b, true);
+  term(-0.5, Ab, &u2, &u2b, Dxh, hb, true);
+  term(0.5, Ab, &uv_, &ub, Dxhu, hub, true);
+  term(-0.5, Ab, &hu, &hub, Dxu, ub, true);
+  term(0.5, Ab, nullptr, nullptr, Dyhuv, huvb, false);
+  term(-0.5, Ab, &uv, &uvb, Dyh, hb, false);
+  term(0.5, Ab, &hv, &hvb, Dyu, ub, false);
+  term(-0.5, Ab, &hu, &hub, Dyv, vb, false);
+  term(lam / 6, Ab, &r2, &r2b, Dxh, hb, true);
+  term(lam / 3, Ab, nullptr, nullptr, Dxeta, etab, true);
+  term(-lam / 3, Ab, &r, &rb, Dxeta, etab, true);
+  term(-lam / 6, Ab, nullptr, nullptr, Dxe2h, e2hb, true);
+  term(lam / 2, Ab, &omr, &omrb, Dxb, bb, true);
+  // B
+  term(g, Bb, nullptr, nullptr, DyhH, hHb, false);
+  term(-g, Bb, &H, &Hb, Dyh, hb, false);
+  term(0.5, Bb, &hv_, &hb, Dyv2, v2b, false);
+  term(-0.5, Bb, &v2, &v2b, Dyh, hb, false);
+  term(0.5, Bb, &vv_, &vb, Dyhv, hvb, false);
+  term(-0.5, Bb, &hv, &hvb, Dyv, vb, false);
+  term(0.5, Bb, nullptr, nullptr, Dxhuv, huvb, true);
+  term(-0.5, Bb, &uv, &uvb, Dxh, hb, true);
+  term(0.5, Bb, &hu, &hub, Dxv, vb, true);
+  term(-0.5, Bb, &hv, &hvb, Dxu, ub, true);
+  term(lam / 6, Bb, &r2, &r2b, Dyh, hb, false);
+  term(lam / 3, Bb, nullptr, nullptr, Dyeta, etab, false);
+  term(-lam / 3, Bb, &r, &rb, Dyeta, etab, false);
+  term(-lam / 6, Bb, nullptr, nullptr, Dye2h, e2hb, false);
+  term(lam / 2, Bb, &omr, &omrb, Dyb, bb, false);
+  // C
+  term(0.5, Cb, nullptr, nullptr, Dxhuw, huwb, true);
+  term(0.5, Cb, &hu, &hub, Dxw, wb, true);
+  term(-0.5, Cb, &uw, &uwb, Dxh, hb, true);
+  term(-0.5, Cb, &hw, &hwb, Dxu, ub, true);
+  term(0.5, Cb, nullptr, nullptr, Dyhvw, hvwb, false);
+  term(0.5, Cb, &hv, &hvb, Dyw, wb, false);
+  term(-0.5, Cb, &vw, &vwb, Dyh, hb, false);
+  term(-0.5, Cb, &hw, &hwb, Dyv, vb, false);
+  // h_t = -(u Dxh + h Dxu + v Dyh + h Dyv) + SATs
+  vec ahv(ah, ah + N);
+  term(-1.0, ahv, &uv_, &ub, Dxh, hb, true);
+  term(-1.0, ahv, &hv_, &hb, Dxu, ub, true);
+  term(-1.0, ahv, &vv_, &vb, Dyh, hb, false);
+  term(-1.0, ahv, &hv_, &hb, Dyv, vb, false);
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      if (gr.bc_x == 1) hub[k] += o.x.bn[i] / o.x.w[i] * ah[k];
+      if (gr.bc_y == 1) hvb[k] += o.y.bn[j] / o.y.w[j] * ah[k];
+    }
+  // eta_t = w - (u Dxeta + v Dyeta + 1.5 u Dxb + 1.5 v Dyb)
+  vec aev(aeta, aeta + N);
+  for (size_t k = 0; k < N; ++k) wb[k] += aeta[k];
+  term(-1.0, aev, &uv_, &ub, Dxeta, etab, true);
+  term(-1.0, aev, &vv_, &vb, Dyeta, etab, false);
+  term(-1.5, aev, &uv_, &ub, Dxb, bb, true);
+  term(-1.5, aev, &vv_, &vb, Dyb, bb, false);
+
+  // chain the pointwise products back to h, u, v, w, eta, b
+  for (size_t k = 0; k < N; ++k) {
+    rb[k] -= omrb[k];
+    hb[k] += H[k] * hHb[k];
+    Hb[k] += h[k] * hHb[k];
+    hb[k] += Hb[k];
+    bb[k] += Hb[k];
+    ub[k] += 2 * u[k] * u2b[k];
+    vb[k] += 2 * v[k] * v2b[k];
+    hb[k] += u[k] * hub[k];
+    ub[k] += h[k] * hub[k];
+    hb[k] += v[k] * hvb[k];
+    vb[k] += h[k] * hvb[k];
+    hb[k] += u[k] * v[k] * huvb[k];
+    ub[k] += h[k] * v[k] * huvb[k];
+    vb[k] += h[k] * u[k] * huvb[k];
+    ub[k] += v[k] * uvb[k];
+    vb[k] += u[k] * uvb[k];
+    etab[k] += 2 * eta[k] / h[k] * e2hb[k];
+    hb[k] += -eta[k] * eta[k] / (h[k] * h[k]) * e2hb[k];
+    hb[k] += u[k] * w[k] * huwb[k];
+    ub[k] += h[k] * w[k] * huwb[k];
+    wb[k] += h[k] * u[k] * huwb[k];
+    hb[k] += v[k] * w[k] * hvwb[k];
+    vb[k] += h[k] * w[k] * hvwb[k];
+    wb[k] += h[k] * v[k] * hvwb[k];
+    ub[k] += w[k] * uwb[k];
+    wb[k] += u[k] * uwb[k];
+    vb[k] += w[k] * vwb[k];
+    wb[k] += v[k] * vwb[k];
+    hb[k] += w[k] * hwb[k];
+    wb[k] += h[k] * hwb[k];
+    etab[k] += rb[k] / h[k];
+    hb[k] += -eta[k] / (h[k] * h[k]) * rb[k];
+    etab[k] += 2 * eta[k] / (h[k] * h[k]) * r2b[k];
+    hb[k] += -2 * eta[k] * eta[k] / (h[k] * h[k] * h[k]) * r2b[k];
+  }
+  for (size_t k = 0; k < N; ++k) {
+    qbar[k] += hb[k];
+    qbar[N + k] += ub[k];
+    qbar[2 * N + k] += vb[k];
+    qbar[3 * N + k] += wb[k];
+    qbar[4 * N + k] += etab[k];
+    if (bbar) bbar[k] += bb[k];
+  }
+}
+
+// Reverse of one classical RK4 step from q_n: on entry qbar is the cotangent of
+// q_{n+1}, on exit that of q_n; bbar accumulates the bathymetry cotangent.
+//   kb4 = dt/6 qb;            Yb4 = J(Y4)^T kb4
+//   kb3 = dt/3 qb + dt Yb4;   Yb3 = J(Y3)^T kb3
+//   kb2 = dt/3 qb + dt/2 Yb3; Yb2 = J(Y2)^T kb2
+//   kb1 = dt/6 qb + dt/2 Yb2; Yb1 = J(Y1)^T kb1
+//   qb_n = qb + Yb1 + Yb2 + Yb3 + Yb4
+void rk4_vjp_impl(const orc_grid& gr, const Ops& o, const double* q, const double* b, double dt, double* qbar,
+                  double* bbar) {
+  const size_t M = 5 * o.N;
+  std::vector<double> k1(M), k2(M), k3(M), Y2(M), Y3(M), Y4(M);
+  rhs_impl<double>(gr, o, q, b, 0.0, 0, k1.data());
+  for (size_t k = 0; k < M; ++k) Y2[k] = q[k] + dt / 2 * k1[k];
+  rhs_impl<double>(gr, o, Y2.data(), b, 0.0, 0, k2.data());
+  for (size_t k = 0; k < M; ++k) Y3[k] = q[k] + dt / 2 * k2[k];
+  rhs_impl<double>(gr, o, Y3.data(), b, 0.0, 0, k3.data());
+  for (size_t k = 0; k < M; ++k) Y4[k] = q[k] + dt * k3[k];
+  std::vector<double> kb(M), Yb4(M, 0), Yb3(M, 0), Yb2(M, 0), Yb1(M, 0);
+  for (size_t k = 0; k < M; ++k) kb[k] = dt / 6 * qbar[k];
+  rhs_vjp_impl(gr, o, Y4.data(), b, kb.data(), Yb4.data(), bbar);
+  for (size_t k = 0; k < M; ++k) kb[k] = dt / 3 * qbar[k] + dt * Yb4[k];
+  rhs_vjp_impl(gr, o, Y3.data(), b, kb.data(), Yb3.data(), bbar);
+  for (size_t k = 0; k < M; ++k) kb[k] = dt / 3 * qbar[k] + dt / 2 * Yb3[k];
+  rhs_vjp_impl(gr, o, Y2.data(), b, kb.data(), Yb2.data(), bbar);
+  for (size_t k = 0; k < M; ++k) kb[k] = dt / 6 * qbar[k] + dt / 2 * Yb2[k];
+  rhs_vjp_impl(gr, o, q, b, kb.data(), Yb1.data(), bbar);
+  for (size_t k = 0; k < M; ++k) qbar[k] = qbar[k] + Yb1[k] + Yb2[k] + Yb3[k] + Yb4[k];
+}
+
+// Gauge-misfit loss of a rollout:  L = 1/2 sum_{n=1..nsteps} sum_g (zeta_g^n - target_{n-1,g})^2,
+// zeta = h + b at gauge nodes, from h0 = zeta0 - b, u0 = v0 = 0 and the
+// auxiliary initialization.  Templated for the complex-step pin.
+template <class T>
+T gauge_loss_impl(const orc_grid& gr, const Ops& o, const T* zeta0, const T* b, double dt, int64_t nsteps,
+                  const int64_t* gidx, int ng, const double* target) {
+  const size_t N = o.N;
+  std::vector<T> q(5 * N, T(0));
+  for (size_t k = 0; k < N; ++k) q[k] = zeta0[k] - b[k];
+  init_aux_impl<T>(o, q.data(), b);
+  T L = T(0);
+  for (int64_t n = 1; n <= nsteps; ++n) {
+    rk4_step_impl<T>(gr, o, q.data(), b, dt, 0.0, 0);
+    for (int gi = 0; gi < ng; ++gi) {
+      const T m = q[gidx[gi]] + b[gidx[gi]] - T(target[(n - 1) * ng + gi]);
+      L += T(0.5) * m * m;
+    }
+  }
+  return L;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -608,6 +863,87 @@ void orc_mms_source(const orc_grid* g, double t, double* S) {
       mms_source_point(g->g, g->lambda, node_x(o, *g, i), node_y(o, *g, j), t, s);
       for (int f = 0; f < 5; ++f) S[f * N + (size_t)j * o.nx + i] = s[f];
     }
+}
+
+void orc_rhs_vjp(const orc_grid* g, const double* q, const double* b, const double* a, double* qbar, double* bbar) {
+  Ops o = make_ops(*g);
+  rhs_vjp_impl(*g, o, q, b, a, qbar, bbar);
+}
+
+void orc_rk4_vjp(const orc_grid* g, const double* q, const double* b, double dt, double* qbar, double* bbar) {
+  Ops o = make_ops(*g);
+  rk4_vjp_impl(*g, o, q, b, dt, qbar, bbar);
+}
+
+// Directional derivative of one RK4 step along (dq, db) by the complex step.
+void orc_rk4_jvp(const orc_grid* g, const double* q, const double* b, double dt, const double* dq, const double* db,
+                 double* out) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  std::vector<cplx> qc(5 * N), bc(N);
+  for (size_t k = 0; k < 5 * N; ++k) qc[k] = cplx(q[k], CS_EPS * dq[k]);
+  for (size_t k = 0; k < N; ++k) bc[k] = cplx(b[k], db ? CS_EPS * db[k] : 0.0);
+  rk4_step_impl<cplx>(*g, o, qc.data(), bc.data(), dt, 0.0, 0);
+  for (size_t k = 0; k < 5 * N; ++k) out[k] = std::imag(qc[k]) / CS_EPS;
+}
+
+// Gauge-misfit loss and its directional derivative along (dzeta0, db) by the
+// complex step (the whole rollout in complex arithmetic).
+void orc_gauge_loss(const orc_grid* g, const double* zeta0, const double* b, double dt, int64_t nsteps,
+                    const int64_t* gidx, int ng, const double* target, const double* dzeta0, const double* db,
+                    double* loss, double* dloss) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N;
+  std::vector<cplx> zc(N), bc(N);
+  for (size_t k = 0; k < N; ++k) {
+    zc[k] = cplx(zeta0[k], dzeta0 ? CS_EPS * dzeta0[k] : 0.0);
+    bc[k] = cplx(b[k], db ? CS_EPS * db[k] : 0.0);
+  }
+  const cplx L = gauge_loss_impl<cplx>(*g, o, zc.data(), bc.data(), dt, nsteps, gidx, ng, target);
+  *loss = std::real(L);
+  if (dloss) *dloss = std::imag(L) / CS_EPS;
+}
+
+// Gradient of the gauge-misfit loss by the discrete adjoint: every state of the
+// rollout is kept, then the steps are reversed with orc_rk4_vjp-equivalent
+// sweeps, and the initialization h0 = zeta0 - b, eta0 = h0, w0(h0, u0 = 0,
+// v0 = 0, b) is reversed last.
+void orc_gauge_loss_grad(const orc_grid* g, const double* zeta0, const double* b, double dt, int64_t nsteps,
+                         const int64_t* gidx, int ng, const double* target, double* loss, double* grad_zeta0,
+                         double* grad_b) {
+  Ops o = make_ops(*g);
+  const size_t N = o.N, M = 5 * N;
+  std::vector<std::vector<double>> states;
+  std::vector<double> q(M, 0.0);
+  for (size_t k = 0; k < N; ++k) q[k] = zeta0[k] - b[k];
+  init_aux_impl<double>(o, q.data(), b);
+  double L = 0.0;
+  std::vector<double> mis((size_t)nsteps * ng);
+  for (int64_t n = 1; n <= nsteps; ++n) {
+    states.push_back(q);
+    rk4_step_impl<double>(*g, o, q.data(), b, dt, 0.0, 0);
+    for (int gi = 0; gi < ng; ++gi) {
+      const double m = q[gidx[gi]] + b[gidx[gi]] - target[(n - 1) * ng + gi];
+      mis[(n - 1) * ng + gi] = m;
+      L += 0.5 * m * m;
+    }
+  }
+  *loss = L;
+  std::vector<double> qb(M, 0.0), bb(N, 0.0);
+  for (int64_t n = nsteps; n >= 1; --n) {
+    for (int gi = 0; gi < ng; ++gi) {
+      qb[gidx[gi]] += mis[(n - 1) * ng + gi];
+      bb[gidx[gi]] += mis[(n - 1) * ng + gi];
+    }
+    rk4_vjp_impl(*g, o, states[n - 1].data(), b, dt, qb.data(), bb.data());
+  }
+  // initialization: eta0 = h0, w0 = -h0 (D_x u0 + D_y v0) + 3/2 (u0 D_x b + v0 D_y b) with u0 = v0 = 0:
+  // w0 does not depend on h0 or b, so h0_bar = qb_h + qb_eta.
+  for (size_t k = 0; k < N; ++k) {
+    const double h0b = qb[k] + qb[4 * N + k];
+    grad_zeta0[k] = h0b;
+    grad_b[k] = bb[k] - h0b;
+  }
 }
 
 }  // extern "C"
