@@ -162,6 +162,44 @@ sgn_status sgn_check(sgn_ctx* ctx);
 sgn_status sgn_spacing(const sgn_ctx* ctx, double* dx, double* dy);
 
 /* ------------------------------------------------------------------------
+ * Discrete adjoint (vector-Jacobian products of the semi-discretization and
+ * of the RK4 step, differentiated after discretization).  Defined without
+ * source terms (SGN_E_UNSUPPORTED otherwise).  Work buffers are allocated on
+ * first use and owned by the context until sgn_destroy.
+ * ------------------------------------------------------------------------ */
+
+/* (qbar, bbar) = J^T a, J the Jacobian of sgn_rhs at q with respect to (q, b).
+ * a, qbar: states; bbar: one plane.  Overwrites qbar and bbar. */
+sgn_status sgn_rhs_vjp(sgn_ctx* ctx, const void* q, const void* a, void* qbar, void* bbar);
+
+/* Reverse of one RK4 step of size dt from q_n.  On entry qbar holds the
+ * cotangent of q_{n+1}; on exit the cotangent of q_n.  bbar accumulates (+=)
+ * the bathymetry cotangent.  The stage states are recomputed (four-stage
+ * path) and reversed in the order k4, k3, k2, k1. */
+sgn_status sgn_step_vjp(sgn_ctx* ctx, const void* q_n, double dt, void* qbar, void* bbar);
+
+/* Gauge series of a rollout: from the initial surface zeta0 (device plane),
+ * h0 = zeta0 - b, u0 = v0 = 0, eta0 = h0 and w0 by eq. (initialization),
+ * advance nsteps RK4 steps of size dt and record zeta = h + b at the gauge
+ * nodes gauge_idx[g] (device int64 row-major node indices, 1..4096 gauges)
+ * after every step into series[n * ngauges + g] (device doubles, n = 0 is the
+ * state after the first step).  Synchronizes. */
+sgn_status sgn_gauge_series(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
+                            int32_t ngauges, double* series);
+
+/* Loss L = 1/2 sum_n sum_g (zeta_g^n - target[n * ngauges + g])^2 over the
+ * rollout of sgn_gauge_series (target: device doubles) and its gradient with
+ * respect to the initial surface (grad_zeta0) and the bathymetry (grad_b),
+ * both device planes.  The forward rollout stores a checkpoint every
+ * checkpoint_every steps (0: ceil(sqrt(nsteps))); the reverse sweep
+ * recomputes one segment at a time, keeping its states and stage states, and
+ * runs the step VJPs backwards.  Memory: checkpoints plus 4*K+1 states for a
+ * segment of K steps.  *loss is a host double.  Synchronizes. */
+sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
+                               int32_t ngauges, const double* target, int64_t checkpoint_every, double* loss,
+                               void* grad_zeta0, void* grad_b);
+
+/* ------------------------------------------------------------------------
  * Ensembles: many independent problems advanced together.
  *
  * Every instance has its own sgn_params (grid size, domain, boundary types, g,

@@ -77,6 +77,11 @@ def load_library() -> ctypes.CDLL:
         "sgn_profile_stages": ([vp, vp, d, ctypes.c_int64, dp], st),
         "sgn_spacing": ([vp, dp, dp], st),
         "sgn_last_error": ([vp], ctypes.c_char_p),
+        "sgn_rhs_vjp": ([vp, cvp, cvp, vp, vp], st),
+        "sgn_step_vjp": ([vp, cvp, d, vp, vp], st),
+        "sgn_gauge_series": ([vp, cvp, ctypes.c_int64, d, cvp, ctypes.c_int32, vp], st),
+        "sgn_gauge_loss_grad": ([vp, cvp, ctypes.c_int64, d, cvp, ctypes.c_int32, cvp, ctypes.c_int64, dp, vp, vp],
+                                st),
         "sgn_batch_create": ([ctypes.c_int32, ctypes.POINTER(SgnParams), vp, ctypes.POINTER(vp)], st),
         "sgn_batch_destroy": ([vp], st),
         "sgn_batch_set_bathymetry": ([vp, ctypes.c_int32, cvp], st),
@@ -241,6 +246,57 @@ class Solver:
 
     def check(self):
         self._chk(self.lib.sgn_check(self.ctx))
+
+    # -- discrete adjoint ------------------------------------------------------
+    def rhs_vjp(self, q, a):
+        """(qbar, bbar) = J^T a for the right-hand side's Jacobian at q."""
+        qbar = self.empty_state()
+        bbar = _torch().empty(self.shape[1:], dtype=self.dtype, device=self.device)
+        self._chk(self.lib.sgn_rhs_vjp(self.ctx, self._state(q), self._state(a, "a"), self._state(qbar, "qbar"),
+                                       self._plane(bbar, "bbar")))
+        return qbar, bbar
+
+    def step_vjp(self, q_n, dt: float, qbar, bbar):
+        """In place: qbar (cotangent of q_{n+1}) becomes that of q_n; bbar accumulates."""
+        self._chk(self.lib.sgn_step_vjp(self.ctx, self._state(q_n), float(dt), self._state(qbar, "qbar"),
+                                        self._plane(bbar, "bbar")))
+
+    def _gauges(self, gauges):
+        torch = _torch()
+        if gauges.dtype != torch.int64 or gauges.device != self.device or gauges.dim() != 1:
+            raise ValueError("gauges must be a 1-D int64 tensor of row-major node indices on the solver's device")
+        n = self.shape[1] * self.shape[2]
+        if gauges.numel() == 0 or int(gauges.min()) < 0 or int(gauges.max()) >= n:
+            raise ValueError("gauge indices out of range")
+        return gauges.contiguous()
+
+    def gauge_series(self, zeta0, nsteps: int, dt: float, gauges):
+        """zeta = h + b at the gauges after each of nsteps steps from surface zeta0 (float64 [nsteps, ng])."""
+        torch = _torch()
+        gauges = self._gauges(gauges)
+        series = torch.empty((int(nsteps), gauges.numel()), dtype=torch.float64, device=self.device)
+        self._chk(self.lib.sgn_gauge_series(self.ctx, self._plane(zeta0, "zeta0"), int(nsteps), float(dt),
+                                            ctypes.c_void_p(gauges.data_ptr()), gauges.numel(),
+                                            ctypes.c_void_p(series.data_ptr())))
+        return series
+
+    def gauge_loss_grad(self, zeta0, nsteps: int, dt: float, gauges, target, checkpoint_every: int = 0):
+        """(L, dL/dzeta0, dL/db) of the gauge misfit; target is float64 [nsteps, ng] on the device."""
+        torch = _torch()
+        gauges = self._gauges(gauges)
+        if tuple(target.shape) != (int(nsteps), gauges.numel()) or target.dtype != torch.float64 or \
+                target.device != self.device:
+            raise ValueError("target must be a float64 [nsteps, ngauges] tensor on the solver's device")
+        target = target.contiguous()
+        gz = torch.empty(self.shape[1:], dtype=self.dtype, device=self.device)
+        gb = torch.empty_like(gz)
+        loss = ctypes.c_double()
+        self._chk(self.lib.sgn_gauge_loss_grad(self.ctx, self._plane(zeta0, "zeta0"), int(nsteps), float(dt),
+                                               ctypes.c_void_p(gauges.data_ptr()), gauges.numel(),
+                                               ctypes.c_void_p(target.data_ptr()), int(checkpoint_every),
+                                               ctypes.byref(loss), ctypes.c_void_p(gz.data_ptr()),
+                                               ctypes.c_void_p(gb.data_ptr())))
+        return loss.value, gz, gb
 
 
 class Batch:

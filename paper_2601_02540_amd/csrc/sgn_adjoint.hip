@@ -1,0 +1,369 @@
+// sgn_adjoint.hip -- discrete adjoint entry points: RHS and RK4-step VJPs and a
+// gauge-misfit loss gradient with sqrt(T) checkpointing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "sgn.h"
+#include "sgn_internal.hpp"
+#include "sgn_reduce.hpp"
+#include "sgn_vjp.hpp"
+
+namespace {
+
+using sgn_host::fail;
+using sgn_host::hip_fail;
+#define HIPCHK(c, expr) SGN_HIPCHK(c, expr)
+
+constexpr int VJP_ROWS = 16;
+
+template <typename T, int ROLE>
+hipError_t launch_vjp_t(const sgn_ctx* c, hipStream_t s, const void* Y, const void* Kin, void* Qb, void* Kout,
+                        void* Acc, void* Bb, double a_in, double cq, double cy) {
+  const int nsx = (c->p.nx + sgn::VJP_STRIP - 1) / sgn::VJP_STRIP;
+  const int nsy = (c->p.ny + VJP_ROWS - 1) / VJP_ROWS;
+  const int items = nsx * nsy;
+  const dim3 grid((unsigned)((items + sgn::VJP_WAVES - 1) / sgn::VJP_WAVES)), block(64 * sgn::VJP_WAVES);
+  const T* Yp = (const T*)Y;
+  const T* bp = (const T*)c->b;
+  const T* kp = (const T*)Kin;
+#define SGN_VJP(BX, BY)                                                                                        \
+  hipLaunchKernelGGL((sgn::vjp_kernel<T, BX, BY, ROLE, VJP_ROWS>), grid, block, 0, s, c->gc, Yp, bp, kp, (T*)Qb, \
+                     (T*)Kout, (T*)Acc, (T*)Bb, (T)a_in, (T)cq, (T)cy)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (bx == 0 && by == 0) SGN_VJP(0, 0);
+  else if (bx == 0 && by == 1) SGN_VJP(0, 1);
+  else if (bx == 1 && by == 0) SGN_VJP(1, 0);
+  else SGN_VJP(1, 1);
+#undef SGN_VJP
+  return hipGetLastError();
+}
+
+template <int ROLE>
+hipError_t launch_vjp(const sgn_ctx* c, hipStream_t s, const void* Y, const void* Kin, void* Qb, void* Kout,
+                      void* Acc, void* Bb, double a_in, double cq, double cy) {
+  if (c->p.dtype == SGN_F64) return launch_vjp_t<double, ROLE>(c, s, Y, Kin, Qb, Kout, Acc, Bb, a_in, cq, cy);
+  return launch_vjp_t<float, ROLE>(c, s, Y, Kin, Qb, Kout, Acc, Bb, a_in, cq, cy);
+}
+
+size_t state_bytes(const sgn_ctx* c) { return 5 * c->N * c->esize; }
+void* slot(void* base, size_t i, const sgn_ctx* c) { return (char*)base + i * state_bytes(c); }
+
+// Cotangent buffers of one step VJP (kb_a, kb_b, accb).
+sgn_status ensure_vjp_buffers(sgn_ctx* c) {
+  auto& a = c->adj;
+  if (a.kb_a) return SGN_OK;
+  if (hipMalloc(&a.kb_a, state_bytes(c)) != hipSuccess || hipMalloc(&a.kb_b, state_bytes(c)) != hipSuccess ||
+      hipMalloc(&a.accb, state_bytes(c)) != hipSuccess) {
+    (void)hipGetLastError();
+    sgn_host::free_adjoint(c);
+    return fail(c, SGN_E_ALLOC, "adjoint buffers");
+  }
+  return SGN_OK;
+}
+
+sgn_status ensure_stage_slots(sgn_ctx* c, size_t slots) {
+  auto& a = c->adj;
+  if (a.stage_slots >= slots) return SGN_OK;
+  if (a.stages) (void)hipFree(a.stages);
+  a.stages = nullptr;
+  a.stage_slots = 0;
+  if (hipMalloc(&a.stages, slots * state_bytes(c)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SGN_E_ALLOC, "adjoint stage storage (" + std::to_string(slots) + " states)");
+  }
+  a.stage_slots = slots;
+  return SGN_OK;
+}
+
+// Forward RK4 step from `qn` into `qout` on the four-stage path, keeping the
+// stage states Y2, Y3, Y4 in `ys` (three consecutive state slots).
+hipError_t forward_step_keep(const sgn_ctx* c, hipStream_t s, const void* qn, void* ys, void* qout, double dt) {
+  void* y2 = slot(ys, 0, c);
+  void* y3 = slot(ys, 1, c);
+  void* y4 = slot(ys, 2, c);
+  hipError_t e;
+  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_FIRST, qn, nullptr, c->acc, y2, dt / 6.0, dt / 2.0, 0.0))) return e;
+  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_MID, y2, qn, c->acc, y3, dt / 3.0, dt / 2.0, 0.0))) return e;
+  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_MID, y3, qn, c->acc, y4, dt / 3.0, dt, 0.0))) return e;
+  return sgn_host::launch_stage_mode(c, s, sgn::MODE_LAST, y4, nullptr, c->acc, qout, dt / 6.0, 0.0, 0.0);
+}
+
+// Reverse of one RK4 step whose stage states are Y1 = qn and ys = (Y2, Y3, Y4).
+// qbar: cotangent of q_{n+1} on entry, of q_n on exit; bbar accumulates.
+hipError_t reverse_step(const sgn_ctx* c, hipStream_t s, const void* qn, const void* ys, void* qbar, void* bbar,
+                        double dt) {
+  const auto& a = c->adj;
+  const void* y2 = slot((void*)ys, 0, c);
+  const void* y3 = slot((void*)ys, 1, c);
+  const void* y4 = slot((void*)ys, 2, c);
+  hipError_t e;
+  // kb4 = dt/6 qb ; next kb3 = dt/3 qb + dt Yb4
+  if ((e = launch_vjp<sgn::VJP_S4>(c, s, y4, qbar, qbar, a.kb_a, a.accb, bbar, dt / 6.0, dt / 3.0, dt))) return e;
+  // kb2 = dt/3 qb + dt/2 Yb3
+  if ((e = launch_vjp<sgn::VJP_S3>(c, s, y3, a.kb_a, qbar, a.kb_b, a.accb, bbar, 1.0, dt / 3.0, dt / 2.0))) return e;
+  // kb1 = dt/6 qb + dt/2 Yb2
+  if ((e = launch_vjp<sgn::VJP_S2>(c, s, y2, a.kb_b, qbar, a.kb_a, a.accb, bbar, 1.0, dt / 6.0, dt / 2.0))) return e;
+  // qb_n = qb + Yb4 + Yb3 + Yb2 + Yb1
+  return launch_vjp<sgn::VJP_S1>(c, s, qn, a.kb_a, qbar, nullptr, a.accb, bbar, 1.0, 0.0, 0.0);
+}
+
+// h = zeta0 - b, u = v = w = 0, eta = h (w is then set by the initialization kernel).
+template <typename T>
+__global__ __launch_bounds__(256) void surface_to_state(const T* __restrict__ zeta0, const T* __restrict__ b,
+                                                        T* __restrict__ q, size_t N) {
+  const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  const T h = zeta0[k] - b[k];
+  q[k] = h;
+  q[N + k] = T(0);
+  q[2 * N + k] = T(0);
+  q[3 * N + k] = T(0);
+  q[4 * N + k] = h;
+}
+
+// zeta = h + b at the gauges, one row of the series.  Also the misfit against a
+// target row and the loss increment (serial over the few gauges, so repeated
+// gauge nodes and the summation order are deterministic).
+// Gauge indices come from the caller: an index outside [0, N) is skipped and
+// raises FLAG_BADINDEX (reported as SGN_E_ARG by the next synchronizing call).
+template <typename T>
+__global__ void gauge_record(const T* __restrict__ q, const T* __restrict__ b, const int64_t* __restrict__ idx,
+                             int ng, size_t N, double* __restrict__ series, const double* __restrict__ target,
+                             double* __restrict__ misfit, double* __restrict__ loss, int* __restrict__ flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    const int64_t k = idx[g];
+    if (k < 0 || (size_t)k >= N) {
+      atomicOr(flag, sgn::FLAG_BADINDEX);
+      if (series) series[g] = 0.0;
+      if (target) misfit[g] = 0.0;
+      continue;
+    }
+    const double z = (double)q[k] + (double)b[k];
+    if (series) series[g] = z;
+    if (target) {
+      const double m = z - target[g];
+      misfit[g] = m;
+      acc += 0.5 * m * m;
+    }
+  }
+  if (loss) *loss += acc;
+}
+
+// Adjoint seed of one misfit row: qbar_h += m and bbar += m at the gauges.
+template <typename T>
+__global__ void gauge_seed(const int64_t* __restrict__ idx, int ng, size_t N, const double* __restrict__ misfit,
+                           T* __restrict__ qbar, T* __restrict__ bbar) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int g = 0; g < ng; ++g) {
+    const int64_t k = idx[g];
+    if (k < 0 || (size_t)k >= N) continue;  // flagged by gauge_record
+    qbar[k] += T(misfit[g]);
+    bbar[k] += T(misfit[g]);
+  }
+}
+
+// grad_zeta0 = hbar0 = qbar_h + qbar_eta; grad_b = bbar - hbar0 (h0 = zeta0 - b,
+// eta0 = h0; with u0 = v0 = 0 the initialized w0 depends on neither).
+template <typename T>
+__global__ __launch_bounds__(256) void init_reverse(const T* __restrict__ qbar, const T* bbar,
+                                                    T* __restrict__ gz, T* gb, size_t N) {
+  const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= N) return;
+  const T h0b = qbar[k] + qbar[4 * N + k];
+  gz[k] = h0b;
+  gb[k] = bbar[k] - h0b;
+}
+
+hipError_t launch_surface(const sgn_ctx* c, const void* zeta0, void* q) {
+  const dim3 grid((unsigned)((c->N + 255) / 256)), block(256);
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(surface_to_state<double>, grid, block, 0, c->stream, (const double*)zeta0, (const double*)c->b,
+                       (double*)q, c->N);
+  else
+    hipLaunchKernelGGL(surface_to_state<float>, grid, block, 0, c->stream, (const float*)zeta0, (const float*)c->b,
+                       (float*)q, c->N);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  const dim3 g2((c->p.nx + 63) / 64, (c->p.ny + 3) / 4);
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(sgn::init_aux_kernel<double>, g2, block, 0, c->stream, c->gc, (double*)q, (const double*)c->b);
+  else
+    hipLaunchKernelGGL(sgn::init_aux_kernel<float>, g2, block, 0, c->stream, c->gc, (float*)q, (const float*)c->b);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const sgn_ctx* c, const void* q, const int64_t* idx, int ng, double* series,
+                         const double* target, double* misfit, double* loss) {
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(gauge_record<double>, dim3(1), dim3(64), 0, c->stream, (const double*)q, (const double*)c->b, idx,
+                       ng, c->N, series, target, misfit, loss, c->flag);
+  else
+    hipLaunchKernelGGL(gauge_record<float>, dim3(1), dim3(64), 0, c->stream, (const float*)q, (const float*)c->b, idx,
+                       ng, c->N, series, target, misfit, loss, c->flag);
+  return hipGetLastError();
+}
+
+sgn_status gauge_args(sgn_ctx* c, const void* zeta0, int64_t nsteps, double dt, const int64_t* idx, int32_t ng) {
+  sgn_status st = sgn_host::check_ctx(c, true);
+  if (st) return st;
+  if (!zeta0 || !idx) return fail(c, SGN_E_ARG, "zeta0 or gauge indices NULL");
+  if (ng <= 0 || ng > 4096) return fail(c, SGN_E_ARG, "need 1..4096 gauges");
+  if (nsteps <= 0) return fail(c, SGN_E_ARG, "nsteps must be > 0");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(c, SGN_E_ARG, "dt must be finite and > 0");
+  if (c->p.source != SGN_SRC_NONE) return fail(c, SGN_E_UNSUPPORTED, "rollouts are defined without source terms");
+  return SGN_OK;
+}
+
+}  // namespace
+
+namespace sgn_host {
+
+void free_adjoint(sgn_ctx* c) {
+  auto& a = c->adj;
+  for (void* p : {a.kb_a, a.kb_b, a.accb, a.qbar, a.state, a.stages, a.ckpt})
+    if (p) (void)hipFree(p);
+  if (a.misfit) (void)hipFree(a.misfit);
+  if (a.loss) (void)hipFree(a.loss);
+  a = AdjointBuffers{};
+}
+
+}  // namespace sgn_host
+
+extern "C" {
+
+sgn_status sgn_rhs_vjp(sgn_ctx* c, const void* q, const void* a, void* qbar, void* bbar) {
+  sgn_status st = sgn_host::check_ctx(c, true);
+  if (st) return st;
+  if (!q || !a || !qbar || !bbar) return fail(c, SGN_E_ARG, "NULL argument");
+  if (c->p.source != SGN_SRC_NONE) return fail(c, SGN_E_UNSUPPORTED, "the VJP is defined without source terms");
+  HIPCHK(c, launch_vjp<sgn::VJP_PLAIN>(c, c->stream, q, a, nullptr, qbar, nullptr, bbar, 1.0, 0.0, 0.0));
+  return SGN_OK;
+}
+
+sgn_status sgn_step_vjp(sgn_ctx* c, const void* q_n, double dt, void* qbar, void* bbar) {
+  sgn_status st = sgn_host::check_ctx(c, true);
+  if (st) return st;
+  if (!q_n || !qbar || !bbar) return fail(c, SGN_E_ARG, "NULL argument");
+  if (!(std::isfinite(dt) && dt > 0)) return fail(c, SGN_E_ARG, "dt must be finite and > 0");
+  if (c->p.source != SGN_SRC_NONE) return fail(c, SGN_E_UNSUPPORTED, "the VJP is defined without source terms");
+  if ((st = ensure_vjp_buffers(c)) || (st = ensure_stage_slots(c, 4))) return st;
+  void* ys = c->adj.stages;
+  void* qnext = slot(c->adj.stages, 3, c);
+  HIPCHK(c, forward_step_keep(c, c->stream, q_n, ys, qnext, dt));
+  HIPCHK(c, reverse_step(c, c->stream, q_n, ys, qbar, bbar, dt));
+  return SGN_OK;
+}
+
+sgn_status sgn_gauge_series(sgn_ctx* c, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
+                            int32_t ngauges, double* series) {
+  sgn_status st = gauge_args(c, zeta0, nsteps, dt, gauge_idx, ngauges);
+  if (st) return st;
+  if (!series) return fail(c, SGN_E_ARG, "series is NULL");
+  auto& a = c->adj;
+  if (!a.state && hipMalloc(&a.state, state_bytes(c)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, SGN_E_ALLOC, "rollout state");
+  }
+  HIPCHK(c, launch_surface(c, zeta0, a.state));
+  void* cur = a.state;
+  void* oth = c->acc;
+  for (int64_t n = 1; n <= nsteps; ++n) {
+    HIPCHK(c, sgn_host::enqueue_pair_step(c, c->stream, cur, oth, dt, 0.0));
+    std::swap(cur, oth);
+    HIPCHK(c, launch_record(c, cur, gauge_idx, ngauges, series + (n - 1) * ngauges, nullptr, nullptr, nullptr));
+  }
+  return sgn_host::sync_results(c, 0);
+}
+
+sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
+                               int32_t ngauges, const double* target, int64_t checkpoint_every, double* loss,
+                               void* grad_zeta0, void* grad_b) {
+  sgn_status st = gauge_args(c, zeta0, nsteps, dt, gauge_idx, ngauges);
+  if (st) return st;
+  if (!target || !loss || !grad_zeta0 || !grad_b) return fail(c, SGN_E_ARG, "NULL argument");
+  int64_t K = checkpoint_every > 0 ? checkpoint_every : (int64_t)std::ceil(std::sqrt((double)nsteps));
+  K = std::max<int64_t>(1, std::min<int64_t>(K, nsteps));
+  const int64_t nseg = (nsteps + K - 1) / K;
+  auto& a = c->adj;
+  if ((st = ensure_vjp_buffers(c)) || (st = ensure_stage_slots(c, (size_t)(4 * K + 1)))) return st;
+  const size_t sb = state_bytes(c);
+  bool ok = true;
+  if (!a.state) ok = ok && hipMalloc(&a.state, sb) == hipSuccess;
+  if (!a.qbar) ok = ok && hipMalloc(&a.qbar, sb) == hipSuccess;
+  if (a.ckpt_slots < (size_t)nseg) {
+    if (a.ckpt) (void)hipFree(a.ckpt);
+    a.ckpt = nullptr;
+    a.ckpt_slots = 0;
+    ok = ok && hipMalloc(&a.ckpt, (size_t)nseg * sb) == hipSuccess;
+    if (ok) a.ckpt_slots = (size_t)nseg;
+  }
+  const size_t mlen = (size_t)nsteps * (size_t)ngauges;
+  if (a.misfit_len < mlen) {
+    if (a.misfit) (void)hipFree(a.misfit);
+    a.misfit = nullptr;
+    a.misfit_len = 0;
+    ok = ok && hipMalloc((void**)&a.misfit, mlen * sizeof(double)) == hipSuccess;
+    if (ok) a.misfit_len = mlen;
+  }
+  if (!a.loss) ok = ok && hipMalloc((void**)&a.loss, sizeof(double)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return fail(c, SGN_E_ALLOC, "adjoint rollout storage");
+  }
+  hipStream_t s = c->stream;
+  // 1. forward rollout on the pair path: checkpoints every K steps, misfits, loss
+  HIPCHK(c, hipMemsetAsync(a.loss, 0, sizeof(double), s));
+  HIPCHK(c, launch_surface(c, zeta0, a.state));
+  void* cur = a.state;
+  void* oth = c->acc;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    if (n % K == 0) HIPCHK(c, hipMemcpyAsync(slot(a.ckpt, (size_t)(n / K), c), cur, sb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, sgn_host::enqueue_pair_step(c, s, cur, oth, dt, 0.0));
+    std::swap(cur, oth);
+    HIPCHK(c, launch_record(c, cur, gauge_idx, ngauges, nullptr, target + n * ngauges, a.misfit + n * ngauges, a.loss));
+  }
+  // 2. reverse sweep, one segment at a time: recompute the segment keeping every
+  //    state and stage state, then reverse its steps
+  HIPCHK(c, hipMemsetAsync(a.qbar, 0, sb, s));
+  HIPCHK(c, hipMemsetAsync(grad_b, 0, c->N * c->esize, s));
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t n0 = seg * K;
+    const int64_t len = std::min<int64_t>(K, nsteps - n0);
+    // slot layout: states 0..len at slots [0, len], stage triples from slot len+1
+    HIPCHK(c, hipMemcpyAsync(slot(a.stages, 0, c), slot(a.ckpt, (size_t)seg, c), sb, hipMemcpyDeviceToDevice, s));
+    for (int64_t k = 0; k < len; ++k)
+      HIPCHK(c, forward_step_keep(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),
+                                  slot(a.stages, (size_t)(k + 1), c), dt));
+    for (int64_t k = len - 1; k >= 0; --k) {
+      const int64_t n = n0 + k;  // step n maps q_n to q_{n+1}; misfit row n belongs to q_{n+1}
+      if (c->p.dtype == SGN_F64)
+        hipLaunchKernelGGL(gauge_seed<double>, dim3(1), dim3(64), 0, s, gauge_idx, ngauges, c->N,
+                           a.misfit + n * ngauges, (double*)a.qbar, (double*)grad_b);
+      else
+        hipLaunchKernelGGL(gauge_seed<float>, dim3(1), dim3(64), 0, s, gauge_idx, ngauges, c->N,
+                           a.misfit + n * ngauges, (float*)a.qbar, (float*)grad_b);
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, reverse_step(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),
+                             a.qbar, grad_b, dt));
+    }
+  }
+  // 3. reverse of the initialization
+  const dim3 grid((unsigned)((c->N + 255) / 256)), block(256);
+  if (c->p.dtype == SGN_F64)
+    hipLaunchKernelGGL(init_reverse<double>, grid, block, 0, s, (const double*)a.qbar, (const double*)grad_b,
+                       (double*)grad_zeta0, (double*)grad_b, c->N);
+  else
+    hipLaunchKernelGGL(init_reverse<float>, grid, block, 0, s, (const float*)a.qbar, (const float*)grad_b,
+                       (float*)grad_zeta0, (float*)grad_b, c->N);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemcpyAsync(c->host_result, a.loss, sizeof(double), hipMemcpyDeviceToHost, s));
+  if ((st = sgn_host::sync_results(c, 0))) return st;
+  *loss = c->host_result[0];
+  return SGN_OK;
+}
+
+}  // extern "C"

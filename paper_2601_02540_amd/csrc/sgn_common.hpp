@@ -16,7 +16,7 @@ enum : int { BC_PERIODIC = 0, BC_REFLECTING = 1 };
 enum : int { MODE_RHS = 0, MODE_FIRST = 1, MODE_MID = 2, MODE_LAST = 3 };
 
 // Health flag bits raised by kernels.
-enum : int { FLAG_NONPOS = 1, FLAG_NONFINITE = 2 };
+enum : int { FLAG_NONPOS = 1, FLAG_NONFINITE = 2, FLAG_BADINDEX = 4 };
 
 // Grid constants passed by value to every kernel.
 struct GridConst {

@@ -1,0 +1,84 @@
+// sgn_internal.hpp -- host-side context shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "sgn.h"
+#include "sgn_common.hpp"
+
+namespace sgn_host {
+
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  const void* q = nullptr;
+  double dt = 0.0;
+  int steps = 0;
+  int path = -1;
+  int tile_y = 0;
+};
+
+// Buffers of the discrete adjoint, allocated on first use and kept by the context.
+struct AdjointBuffers {
+  void* kb_a = nullptr;   // stage cotangents (ping-pong)
+  void* kb_b = nullptr;
+  void* accb = nullptr;   // running sum of the stage cotangents of one step
+  void* qbar = nullptr;   // cotangent of the state
+  void* state = nullptr;  // state of a rollout
+  void* stages = nullptr; // per-step stored states of a segment: (steps+1) states and 3 stage states per step
+  size_t stage_slots = 0; // number of state-sized slots in `stages`
+  void* ckpt = nullptr;   // checkpoints
+  size_t ckpt_slots = 0;
+  double* misfit = nullptr;  // nsteps * ngauges misfits of the forward rollout
+  size_t misfit_len = 0;
+  double* loss = nullptr;    // device accumulator
+};
+
+}  // namespace sgn_host
+
+struct sgn_ctx {
+  sgn_params p{};
+  sgn::GridConst gc{};
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = 0;
+  size_t N = 0;
+  size_t esize = 0;
+  void* b = nullptr;
+  void* acc = nullptr;
+  void* ya = nullptr;
+  void* yb = nullptr;
+  double* partials = nullptr;
+  double* result = nullptr;
+  double* host_result = nullptr;
+  int* flag = nullptr;
+  int* host_flag = nullptr;
+  bool b_set = false;
+  int step_path = SGN_PATH_PAIRS;
+  int tile_y = 8;
+  sgn_host::GraphCache graphs[2];
+  sgn_host::AdjointBuffers adj;
+  std::string err;
+};
+
+namespace sgn_host {
+
+sgn_status fail(sgn_ctx* c, sgn_status st, const std::string& msg);
+sgn_status hip_fail(sgn_ctx* c, hipError_t e, const char* what);
+sgn_status sync_results(sgn_ctx* c, int nres);
+sgn_status check_ctx(sgn_ctx* c, bool need_b);
+void free_adjoint(sgn_ctx* c);
+// stage kernel of the four-stage path in mode `mode` (sgn::MODE_*)
+hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const void* Y, const void* qn, void* acc,
+                             void* out, double c_acc, double c_y, double t);
+// one RK4 step on the pair path from `cur` into `oth`
+hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t);
+
+}  // namespace sgn_host
+
+#define SGN_HIPCHK(c, expr)                                                \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) return sgn_host::hip_fail((c), e_, #expr);       \
+  } while (0)

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "sgn.h"
+#include "sgn_internal.hpp"
 #include "sgn_reduce.hpp"
 #include "sgn_pair.hpp"
 #include "sgn_stage.hpp"
@@ -18,42 +19,11 @@ thread_local std::string g_create_error;
 // Steps captured per graph replay (even, so the pair path returns to q).
 constexpr int GRAPH_STEPS = 8;
 
-struct GraphCache {
-  hipGraphExec_t exec = nullptr;
-  const void* q = nullptr;
-  double dt = 0.0;
-  int steps = 0;
-  int path = -1;
-  int tile_y = 0;
-};
+using sgn_host::GraphCache;
 
 }  // namespace
 
-struct sgn_ctx {
-  sgn_params p{};
-  sgn::GridConst gc{};
-  hipStream_t stream = nullptr;
-  hipStream_t cap_stream = nullptr;
-  int device = 0;
-  size_t N = 0;
-  size_t esize = 0;
-  void* b = nullptr;
-  void* acc = nullptr;
-  void* ya = nullptr;
-  void* yb = nullptr;
-  double* partials = nullptr;
-  double* result = nullptr;
-  double* host_result = nullptr;
-  int* flag = nullptr;
-  int* host_flag = nullptr;
-  bool b_set = false;
-  int step_path = SGN_PATH_PAIRS;
-  int tile_y = 8;
-  GraphCache graphs[2];
-  std::string err;
-};
-
-namespace {
+namespace sgn_host {
 
 sgn_status fail(sgn_ctx* c, sgn_status st, const std::string& msg) {
   if (c)
@@ -67,11 +37,14 @@ sgn_status hip_fail(sgn_ctx* c, hipError_t e, const char* what) {
   return fail(c, SGN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(c, expr)                                  \
-  do {                                                   \
-    hipError_t e_ = (expr);                              \
-    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
-  } while (0)
+}  // namespace sgn_host
+
+namespace {
+
+using sgn_host::fail;
+using sgn_host::hip_fail;
+
+#define HIPCHK(c, expr) SGN_HIPCHK(c, expr)
 
 double axis_spacing(int n, double lo, double hi, int bc) {
   return bc == SGN_PERIODIC ? (hi - lo) / n : (hi - lo) / (n - 1);
@@ -246,6 +219,10 @@ sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGra
   return SGN_OK;
 }
 
+}  // namespace
+
+namespace sgn_host {
+
 // Copies the health flag and `nres` result doubles to host, synchronizes, and
 // converts a raised flag into a status (clearing it).
 sgn_status sync_results(sgn_ctx* c, int nres) {
@@ -256,11 +233,39 @@ sgn_status sync_results(sgn_ctx* c, int nres) {
   if (f) {
     HIPCHK(c, hipMemsetAsync(c->flag, 0, sizeof(int), c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f & sgn::FLAG_BADINDEX) return fail(c, SGN_E_ARG, "a gauge index lies outside the grid");
     if (f & sgn::FLAG_NONFINITE) return fail(c, SGN_E_NONFINITE, "a step produced a non-finite value");
     return fail(c, SGN_E_NONPOS_DEPTH, "a step produced h <= 0 (the method has no wetting/drying)");
   }
   return SGN_OK;
 }
+
+sgn_status check_ctx(sgn_ctx* c, bool need_b) {
+  if (!c) return SGN_E_ARG;
+  if (need_b && !c->b_set) return fail(c, SGN_E_STATE, "bathymetry not set (call sgn_set_bathymetry first)");
+  return SGN_OK;
+}
+
+hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const void* Y, const void* qn, void* acc,
+                             void* out, double c_acc, double c_y, double t) {
+  switch (mode) {
+    case sgn::MODE_RHS: return launch_stage<sgn::MODE_RHS>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+    case sgn::MODE_FIRST: return launch_stage<sgn::MODE_FIRST>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+    case sgn::MODE_MID: return launch_stage<sgn::MODE_MID>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+    default: return launch_stage<sgn::MODE_LAST>(c, s, Y, qn, acc, out, c_acc, c_y, t);
+  }
+}
+
+hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {
+  return ::enqueue_pair_step(c, s, cur, oth, dt, t);
+}
+
+}  // namespace sgn_host
+
+namespace {
+
+using sgn_host::sync_results;
+using sgn_host::check_ctx;
 
 template <typename T>
 hipError_t launch_totals(const sgn_ctx* c, const void* q, const void* dq, int what) {
@@ -275,11 +280,6 @@ hipError_t launch_totals(const sgn_ctx* c, const void* q, const void* dq, int wh
   return hipGetLastError();
 }
 
-sgn_status check_ctx(sgn_ctx* c, bool need_b) {
-  if (!c) return SGN_E_ARG;
-  if (need_b && !c->b_set) return fail(c, SGN_E_STATE, "bathymetry not set (call sgn_set_bathymetry first)");
-  return SGN_OK;
-}
 
 }  // namespace
 
@@ -373,6 +373,7 @@ sgn_status sgn_destroy(sgn_ctx* c) {
   if (!c) return SGN_OK;
   (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
+  sgn_host::free_adjoint(c);
   if (c->b) (void)hipFree(c->b);
   if (c->acc) (void)hipFree(c->acc);
   if (c->ya) (void)hipFree(c->ya);
