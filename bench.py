@@ -40,6 +40,7 @@ HBM_PEAK_GBS = 8000.0
 #          q, acc and write acc, Y (26 each); stage 4 reads Y, b, acc and writes
 #          q (16)                 -> 84 values, 4 launches
 PATHS = {"pairs": (37, 2), "stages": (84, 4)}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "stages"}
 
 
 def log(msg):
@@ -185,6 +186,54 @@ def run_ensemble(count, steps, warmup, dtype, label):
     return res
 
 
+def run_adjoint(n, steps, label):
+    """adjoint:forward cost on the gauge workload: reflecting [0,30]x[0,10], n^2, FP64, 16 gauges,
+    loss against the series of a target run; gradient wrt the initial surface and the bathymetry."""
+    import numpy as np
+    import torch
+    from paper_2601_02540_amd import workloads as W
+    from paper_2601_02540_amd.binding import Solver
+
+    gp = W.gauge_problem(n, seed=5)
+    g = gp.grid
+    s = Solver(g, torch.float64)
+    nodes = torch.from_numpy(gp.gauges[:, 0] * g.nx + gp.gauges[:, 1]).cuda()
+    z0 = torch.from_numpy(gp.zeta0).cuda()
+    b = torch.from_numpy(gp.b).cuda()
+    q = torch.zeros((5, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    q[0] = z0 - b
+    q[4] = q[0]
+    s.set_bathymetry(b)
+    dt = s.cfl_dt(q, 0.5)
+    s.set_bathymetry(torch.from_numpy(gp.target_b).cuda())
+    target = s.gauge_series(torch.from_numpy(gp.target_zeta0).cuda(), steps, dt, nodes)
+    s.set_bathymetry(b)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    qf = q.clone()
+    s.init_aux(qf)
+    s.step(qf, dt, 8)  # warm-up (graph capture)
+    t_fwd, _ = timed(lambda: s.step(qf, dt, steps))
+    t_series, _ = timed(lambda: s.gauge_series(z0, steps, dt, nodes))
+    s.gauge_loss_grad(z0, 20, dt, nodes, target[:20])  # warm-up of the adjoint buffers
+    t_grad, (L, gz, gb) = timed(lambda: s.gauge_loss_grad(z0, steps, dt, nodes, target))
+    res = {"grid": [g.nx, g.ny], "steps": steps, "gauges": int(len(gp.gauges)), "dt": dt,
+           "checkpoint_every": int(np.ceil(np.sqrt(steps))), "loss": L,
+           "forward_s": t_fwd, "forward_with_gauges_s": t_series, "gradient_s": t_grad,
+           "adjoint_to_forward": t_grad / t_fwd,
+           "grad_norms": {"zeta0": float(torch.linalg.norm(gz)), "b": float(torch.linalg.norm(gb))}}
+    log(f"[{label}] forward {t_fwd:.3f} s, gradient {t_grad:.3f} s, adjoint:forward = {t_grad / t_fwd:.2f}")
+    s.close()
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(problem, steps=1):
     """The FP64 oracle (single thread, as written) on the same workload."""
     import numpy as np
@@ -223,6 +272,10 @@ def main():
     ap.add_argument("--path", choices=sorted(PATHS), default="pairs", help="step path of the main run")
     ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
                     help="tile height (default: the library's per-dtype default)")
+    ap.add_argument("--variants", default="all",
+                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,stages (default all)")
+    ap.add_argument("--ensemble-steps", type=int, default=100)
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
     args = ap.parse_args()
 
@@ -249,18 +302,28 @@ def main():
     main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64", P, T)
 
     variants = {}
-    if not args.no_variants:
+    chosen = set() if args.no_variants else (ALL_VARIANTS if args.variants == "all" else set(args.variants.split(",")))
+    unknown = chosen - ALL_VARIANTS
+    if unknown:
+        raise SystemExit(f"unknown variants: {sorted(unknown)}; choose from {sorted(ALL_VARIANTS)}")
+    if "f32" in chosen:
         variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T)
         variants["periodic_f32"]["energy_diff_vs_f64_rel"] = (
             (variants["periodic_f32"]["energy_final"] - main_res["energy_final"]) / abs(main_res["energy_final"]))
+    if "reflecting" in chosen:
         probr = W.random_phase_large(n, W.REFLECTING, seed=3)
         variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T)
         variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T)
-        variants["ensemble_256_f32"] = run_ensemble(256, 100, 4, torch.float32, "ensemble f32")
+    if "ensemble" in chosen:
+        variants["ensemble_256_f32"] = run_ensemble(256, args.ensemble_steps, 4, torch.float32, "ensemble f32")
+    if "small" in chosen:
         small = W.gaussian_bump_periodic(64, seed=1)
         variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T)
         sol = W.soliton_over_bathymetry(512, seed=2)
         variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T)
+    if "adjoint" in chosen:
+        variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
+    if "stages" in chosen:
         other = "stages" if P == "pairs" else "pairs"
         variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
                                                     f"periodic f64 {other}", other, T)

@@ -340,17 +340,37 @@ __global__ __launch_bounds__(64 * VJP_WAVES) void vjp_kernel(const GridConst gc,
   }
   const T g = T(gc.g), lam = T(gc.lam);
 
-  // rolling window of raw rows j-1, j, j+1 and partial cotangents of rows j-1, j
+  // rolling window of raw rows j-1, j, j+1 (and j+2 in flight) and partial
+  // cotangents of rows j-1, j; the rate cotangents of row j+1 are also fetched
+  // one row ahead, so every load has a row of work to hide behind.
   Node<T> Rm = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart - 2, ny));
   Node<T> R0 = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart - 1, ny));
+  Node<T> Rn = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart, ny));
+  T kbn[5];
+  {
+    const int j = jstart - 1;
+    const bool row_in = BCY == BC_PERIODIC || (j >= 0 && j < ny);
+    const size_t o = (size_t)vjp_wrap<BCY>(j, ny) * nx + gi;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) kbn[f] = (reverse_lane && row_in) ? a_in * Kin[f * N + o] : T(0);
+  }
   Cot<T> Pm, P0;
   Pm.zero();
   P0.zero();
 
   for (int j = jstart - 1; j <= jend; ++j) {
-    const Node<T> Rp = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(j + 1, ny));
+    const Node<T> Rp = Rn;
+    T kb[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) kb[f] = kbn[f];
+    if (j + 1 <= jend) {
+      Rn = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(j + 2, ny));
+      const bool nrow_in = BCY == BC_PERIODIC || (j + 1 >= 0 && j + 1 < ny);
+      const size_t o = (size_t)vjp_wrap<BCY>(j + 1, ny) * nx + gi;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) kbn[f] = (reverse_lane && nrow_in) ? a_in * Kin[f * N + o] : T(0);
+    }
     const bool row_in = BCY == BC_PERIODIC || (j >= 0 && j < ny);
-    const int gj = vjp_wrap<BCY>(j, ny);
     // x neighbours of this row (all lanes take part in the shuffles)
     const Node<T> XM = shfl_node_left(R0);
     const Node<T> XP = shfl_node_right(R0);
@@ -379,10 +399,6 @@ __global__ __launch_bounds__(64 * VJP_WAVES) void vjp_kernel(const GridConst gc,
       const Node<T>& xp = opx == 0 ? R0 : XP;
       const Node<T>& ym = omy == 0 ? R0 : Rm;
       const Node<T>& yp = opy == 0 ? R0 : Rp;
-      T kb[5];
-      const size_t o = (size_t)gj * nx + gi;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) kb[f] = a_in * Kin[f * N + o];
       T dX[12], dY[12];
       split_form_reverse<T>(R0, xm, xp, ym, yp, sx, sy, g, lam, satx, saty, kb, cen, dX, dY);
       T ax[12], ay[12];
