@@ -221,7 +221,8 @@ def run_adjoint(n, steps, label):
     s.step(qf, dt, 8)  # warm-up (graph capture)
     t_fwd, _ = timed(lambda: s.step(qf, dt, steps))
     t_series, _ = timed(lambda: s.gauge_series(z0, steps, dt, nodes))
-    s.gauge_loss_grad(z0, 20, dt, nodes, target[:20])  # warm-up of the adjoint buffers
+    w = min(20, steps)
+    s.gauge_loss_grad(z0, w, dt, nodes, target[:w].contiguous())  # warm-up of the adjoint buffers
     t_grad, (L, gz, gb) = timed(lambda: s.gauge_loss_grad(z0, steps, dt, nodes, target))
     res = {"grid": [g.nx, g.ny], "steps": steps, "gauges": int(len(gp.gauges)), "dt": dt,
            "checkpoint_every": int(np.ceil(np.sqrt(steps))), "loss": L,

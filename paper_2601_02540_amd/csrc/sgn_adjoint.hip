@@ -9,6 +9,7 @@
 #include "sgn.h"
 #include "sgn_internal.hpp"
 #include "sgn_reduce.hpp"
+#include "sgn_pair.hpp"
 #include "sgn_vjp.hpp"
 
 namespace {
@@ -17,20 +18,19 @@ using sgn_host::fail;
 using sgn_host::hip_fail;
 #define HIPCHK(c, expr) SGN_HIPCHK(c, expr)
 
-constexpr int VJP_ROWS = 8;
+constexpr int VJP_TY = 4;
 
 template <typename T, int ROLE>
 hipError_t launch_vjp_t(const sgn_ctx* c, hipStream_t s, const void* Y, const void* Kin, void* Qb, void* Kout,
                         void* Acc, void* Bb, double a_in, double cq, double cy) {
-  const int nsx = (c->p.nx + sgn::VJP_STRIP - 1) / sgn::VJP_STRIP;
-  const int nsy = (c->p.ny + VJP_ROWS - 1) / VJP_ROWS;
-  const int items = nsx * nsy;
-  const dim3 grid((unsigned)((items + sgn::VJP_WAVES - 1) / sgn::VJP_WAVES)), block(64 * sgn::VJP_WAVES);
+  const int ntx = (c->p.nx + sgn::TILE_X - 1) / sgn::TILE_X;
+  const int nty = (c->p.ny + VJP_TY - 1) / VJP_TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
   const T* Yp = (const T*)Y;
   const T* bp = (const T*)c->b;
   const T* kp = (const T*)Kin;
-#define SGN_VJP(BX, BY)                                                                                        \
-  hipLaunchKernelGGL((sgn::vjp_kernel<T, BX, BY, ROLE, VJP_ROWS>), grid, block, 0, s, c->gc, Yp, bp, kp, (T*)Qb, \
+#define SGN_VJP(BX, BY)                                                                                       \
+  hipLaunchKernelGGL((sgn::vjp_kernel<T, BX, BY, ROLE, VJP_TY>), grid, block, 0, s, c->gc, Yp, bp, kp, (T*)Qb, \
                      (T*)Kout, (T*)Acc, (T*)Bb, (T)a_in, (T)cq, (T)cy)
   const int bx = c->p.bc_x, by = c->p.bc_y;
   if (bx == 0 && by == 0) SGN_VJP(0, 0);
@@ -78,17 +78,51 @@ sgn_status ensure_stage_slots(sgn_ctx* c, size_t slots) {
   return SGN_OK;
 }
 
-// Forward RK4 step from `qn` into `qout` on the four-stage path, keeping the
-// stage states Y2, Y3, Y4 in `ys` (three consecutive state slots).
+template <typename T, int PAIR, int TY>
+hipError_t launch_pair_save_t(const sgn_ctx* c, hipStream_t s, const void* Yin, const void* qn, void* acc,
+                              void* yb, void* ysave, void* qout, double c1_acc, double c1_y, double c2_acc,
+                              double c2_y) {
+  const int ntx = (c->p.nx + sgn::TILE_X - 1) / sgn::TILE_X;
+  const int nty = (c->p.ny + TY - 1) / TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
+#define SGN_PS(BX, BY)                                                                                         \
+  hipLaunchKernelGGL((sgn::pair_save_kernel<T, BX, BY, PAIR, TY>), grid, block, 0, s, c->gc, (const T*)Yin,      \
+                     (const T*)c->b, (const T*)qn, (T*)acc, (T*)yb, (T*)ysave, (T*)qout, (T)c1_acc, (T)c1_y, \
+                     (T)c2_acc, (T)c2_y, c->flag)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (bx == 0 && by == 0) SGN_PS(0, 0);
+  else if (bx == 0 && by == 1) SGN_PS(0, 1);
+  else if (bx == 1 && by == 0) SGN_PS(1, 0);
+  else SGN_PS(1, 1);
+#undef SGN_PS
+  return hipGetLastError();
+}
+
+template <int PAIR>
+hipError_t launch_pair_save(const sgn_ctx* c, hipStream_t s, const void* Yin, const void* qn, void* acc, void* yb,
+                            void* ysave, void* qout, double c1_acc, double c1_y, double c2_acc, double c2_y) {
+  if (c->p.dtype == SGN_F64) {
+    if (c->tile_y == 16)
+      return launch_pair_save_t<double, PAIR, 16>(c, s, Yin, qn, acc, yb, ysave, qout, c1_acc, c1_y, c2_acc, c2_y);
+    return launch_pair_save_t<double, PAIR, 8>(c, s, Yin, qn, acc, yb, ysave, qout, c1_acc, c1_y, c2_acc, c2_y);
+  }
+  if (c->tile_y == 16)
+    return launch_pair_save_t<float, PAIR, 16>(c, s, Yin, qn, acc, yb, ysave, qout, c1_acc, c1_y, c2_acc, c2_y);
+  return launch_pair_save_t<float, PAIR, 8>(c, s, Yin, qn, acc, yb, ysave, qout, c1_acc, c1_y, c2_acc, c2_y);
+}
+
+// Forward RK4 step from `qn` into `qout` on the pair path, keeping the stage
+// states Y2, Y3, Y4 in `ys` (three consecutive state slots):
+//   pair 1: k1 = f(qn), Y2 = qn + dt/2 k1 (saved), k2 = f(Y2), acc, Y3 = qn + dt/2 k2
+//   pair 2: k3 = f(Y3), Y4 = qn + dt k3 (saved), k4 = f(Y4), qout = acc + dt/3 k3 + dt/6 k4
 hipError_t forward_step_keep(const sgn_ctx* c, hipStream_t s, const void* qn, void* ys, void* qout, double dt) {
   void* y2 = slot(ys, 0, c);
   void* y3 = slot(ys, 1, c);
   void* y4 = slot(ys, 2, c);
-  hipError_t e;
-  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_FIRST, qn, nullptr, c->acc, y2, dt / 6.0, dt / 2.0, 0.0))) return e;
-  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_MID, y2, qn, c->acc, y3, dt / 3.0, dt / 2.0, 0.0))) return e;
-  if ((e = sgn_host::launch_stage_mode(c, s, sgn::MODE_MID, y3, qn, c->acc, y4, dt / 3.0, dt, 0.0))) return e;
-  return sgn_host::launch_stage_mode(c, s, sgn::MODE_LAST, y4, nullptr, c->acc, qout, dt / 6.0, 0.0, 0.0);
+  hipError_t e = launch_pair_save<1>(c, s, qn, nullptr, c->acc, y3, y2, nullptr, dt / 6.0, dt / 2.0, dt / 3.0,
+                                     dt / 2.0);
+  if (e) return e;
+  return launch_pair_save<2>(c, s, y3, qn, c->acc, nullptr, y4, qout, dt / 3.0, dt, dt / 6.0, 0.0);
 }
 
 // Reverse of one RK4 step whose stage states are Y1 = qn and ys = (Y2, Y3, Y4).

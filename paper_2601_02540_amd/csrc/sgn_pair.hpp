@@ -101,11 +101,15 @@ __device__ __forceinline__ Rates<T> pair_eval(const PairSmem<T, TY>& s, int r, i
 // PAIR = 1: Yin = q (state), writes acc_io = acc and yb_out = Yb.
 // PAIR = 2: Yin = Yb, qn = q (state), acc_io holds acc on entry and q_new on exit.
 // The caller synchronizes the workgroup before reusing `s` for another tile.
-template <typename T, int BCX, int BCY, int PAIR, bool SRC, int TY>
+// SAVE (adjoint recomputation): also write the intermediate stage of owned
+// nodes to ysave (pair 1: Y2 = q + dt/2 k1; pair 2: Y4 = q + dt k3), and in
+// pair 2 write q_new to qout instead of over acc.
+template <typename T, int BCX, int BCY, int PAIR, bool SRC, int TY, bool SAVE = false>
 __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& gc, int i0, int j0,
                                           const T* __restrict__ Yin, const T* __restrict__ bplane,
                                           const T* __restrict__ qn, T* acc_io, T* __restrict__ yb_out, T c1_acc,
-                                          T c1_y, T c2_acc, T c2_y, double t1, double t2, int* __restrict__ flag) {
+                                          T c1_y, T c2_acc, T c2_y, double t1, double t2, int* __restrict__ flag,
+                                          T* __restrict__ ysave = nullptr, T* __restrict__ qout = nullptr) {
   static_assert(TY % THREAD_ROWS == 0, "tile height must be a multiple of 4");
   constexpr int RPT = TY / THREAD_ROWS;
   constexpr int W2 = TILE_X + 4;
@@ -241,6 +245,13 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
   for (int k = 0; k < RPT; ++k) {
     if (!in_dom[k]) continue;
     const int r = ty + k * THREAD_ROWS + 2, c = tx + 2;
+    if (SAVE) {
+      const int j = j0 + ty + k * THREAD_ROWS;
+      if (i < nx && j < ny) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) ysave[f * N + (size_t)j * nx + i] = mid[k][f];
+      }
+    }
 #pragma unroll
     for (int f = 0; f < 5; ++f) s.f[f][r][c] = mid[k][f];
     s.f[6][r][c] = T(1) / mid[k][0];
@@ -272,10 +283,11 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
       }
     } else {
       T nv[5];
+      T* dst = SAVE ? qout : acc_io;
 #pragma unroll
       for (int f = 0; f < 5; ++f) {
         nv[f] = accr[k][f] + c2_acc * kv[f];
-        acc_io[f * N + o] = nv[f];
+        dst[f * N + o] = nv[f];
       }
       if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
       const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
@@ -297,6 +309,24 @@ __global__ __launch_bounds__(STAGE_THREADS) void pair_kernel(const GridConst gc,
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
   pair_tile<T, BCX, BCY, PAIR, SRC, TY>(s, gc, (tile % ntx) * TILE_X, (tile / ntx) * TY, Yin, bplane, qn, acc_io,
                                         yb_out, c1_acc, c1_y, c2_acc, c2_y, t1, t2, flag);
+}
+
+// Pair kernel of the adjoint's segment recomputation (no source terms): the
+// same tile code with the intermediate stages saved (see pair_tile, SAVE).
+template <typename T, int BCX, int BCY, int PAIR, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void pair_save_kernel(const GridConst gc, const T* __restrict__ Yin,
+                                                                  const T* __restrict__ bplane,
+                                                                  const T* __restrict__ qn, T* acc_io,
+                                                                  T* __restrict__ yb_out, T* __restrict__ ysave,
+                                                                  T* __restrict__ qout, T c1_acc, T c1_y, T c2_acc,
+                                                                  T c2_y, int* __restrict__ flag) {
+  __shared__ PairSmem<T, TY> s;
+  const int ntx = (gc.nx + TILE_X - 1) / TILE_X;
+  const int nty = (gc.ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  pair_tile<T, BCX, BCY, PAIR, false, TY, true>(s, gc, (tile % ntx) * TILE_X, (tile / ntx) * TY, Yin, bplane, qn,
+                                                acc_io, yb_out, c1_acc, c1_y, c2_acc, c2_y, 0.0, 0.0, flag, ysave,
+                                                qout);
 }
 
 }  // namespace sgn

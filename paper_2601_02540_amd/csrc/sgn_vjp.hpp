@@ -11,20 +11,19 @@
 // back to that node's raw values.  The cotangent of node d is the sum of what
 // d and its four neighbours send to it -- the transpose of the stencil.
 //
-// Layout of the work: a wavefront owns a strip of 64 consecutive columns and
-// walks down a block of rows.  Lane L holds column c0 - 2 + L; lanes 1..62
-// reverse their node, lanes 2..61 own the 60 output columns.  Row-wise
-// contributions cross lanes by shuffles; column-wise ones stay in the lane's
-// registers from one row to the next (rows j-1, j, j+1 of raw values are kept
-// in a rolling window), so no LDS is needed.
+// The cotangent a derivative D f(c) sends out, Dbar_f(c), depends only on node
+// c's own state and rate cotangent (it is the factor multiplying D f in the
+// rates, times the seed), not on any derivative.  The kernel therefore works
+// in gather form, like the forward stencil: node d evaluates Dbar_f at its
+// neighbours from their LDS values and applies the transposed operator column
+//   (D^T Dbar)(d) = D[d-1][d] Dbar(d-1) + D[d][d] Dbar(d) + D[d+1][d] Dbar(d+1)
+// (AxisTranspose below, closure rows included), then chains the amounts back
+// through the products at d.  No value crosses threads except through LDS.
 #pragma once
 
 #include "sgn_stage.hpp"
 
 namespace sgn {
-
-constexpr int VJP_STRIP = 60;  // output columns per wavefront
-constexpr int VJP_WAVES = 4;   // wavefronts per workgroup (independent strips)
 
 // Reverse-mode stage roles.  Cotangent of the step output: Qb.
 //   PLAIN: kb = Kin;           out = Ybar (5 planes), bout = bbar      (rhs VJP)
@@ -240,233 +239,239 @@ __device__ __forceinline__ void split_form_reverse(const Node<T>& c, const Node<
   cen.b = bb;
 }
 
-template <typename T>
-__device__ __forceinline__ T shfl_from_left(T x) {  // value of lane L-1
-  return __shfl_up(x, 1, 64);
-}
-template <typename T>
-__device__ __forceinline__ T shfl_from_right(T x) {  // value of lane L+1
-  return __shfl_down(x, 1, 64);
-}
-template <typename T>
-__device__ __forceinline__ Node<T> shfl_node_left(const Node<T>& n) {
-  Node<T> o;
-  o.h = shfl_from_left(n.h);
-  o.u = shfl_from_left(n.u);
-  o.v = shfl_from_left(n.v);
-  o.w = shfl_from_left(n.w);
-  o.eta = shfl_from_left(n.eta);
-  o.b = shfl_from_left(n.b);
-  o.ih = shfl_from_left(n.ih);
-  return o;
-}
-template <typename T>
-__device__ __forceinline__ Node<T> shfl_node_right(const Node<T>& n) {
-  Node<T> o;
-  o.h = shfl_from_right(n.h);
-  o.u = shfl_from_right(n.u);
-  o.v = shfl_from_right(n.v);
-  o.w = shfl_from_right(n.w);
-  o.eta = shfl_from_right(n.eta);
-  o.b = shfl_from_right(n.b);
-  o.ih = shfl_from_right(n.ih);
-  return o;
-}
-
-template <int BC>
-__device__ __forceinline__ int vjp_wrap(int g, int n) {
-  if (BC == BC_PERIODIC) {
-    if (g < 0) g += n;
-    while (g >= n) g -= n;
-    return g;
+// Column d of the 1D operator: weights of Dbar(d-1), Dbar(d), Dbar(d+1) in
+// (D^T Dbar)(d).  Interior/periodic rows are (-1, 0, 1)/(2 delta); the
+// reflecting first and last rows are (-2, 2)/(2 delta) (n >= 4 assumed).
+template <typename T, int BC>
+struct AxisTranspose {
+  T wl, wc, wr;
+  __device__ __forceinline__ AxisTranspose(int i, int n, double inv2d, double invd) {
+    wl = T(inv2d);
+    wc = T(0);
+    wr = T(-inv2d);
+    if (BC == BC_REFLECTING) {
+      if (i == 0) {
+        wl = T(0);
+        wc = T(-invd);
+      } else if (i == 1) {
+        wl = T(invd);
+      }
+      if (i == n - 1) {
+        wr = T(0);
+        wc = T(invd);
+      } else if (i == n - 2) {
+        wr = T(-invd);
+      }
+    }
   }
-  return g < 0 ? 0 : (g >= n ? n - 1 : g);
+};
+
+template <typename T>
+struct Seed {
+  T h, u, v, w, eta;  // cotangent of the five rates at one node
+};
+
+// Dbar of the 12 x-quantities (h u v w eta b h(h+b) u^2 hu huv eta^2/h huw) at
+// a node from its own state n and seed a: the factor of each D_x f in the
+// rates of eq. (sd_periodic_2D_SGN), times the seed of that rate.
+template <typename T>
+__device__ __forceinline__ void dbar_x(const Node<T>& n, const Seed<T>& a, T g, T lam, T (&q)[12]) {
+  const T half = T(0.5);
+  const T ih = n.ih;
+  const T Ab = -a.u * ih, Bb = -a.v * ih, Cb = -a.w * ih;
+  const T H = n.h + n.b, r = n.eta * ih, omr = T(1) - r;
+  const T hu = n.h * n.u, hv = n.h * n.v, hw = n.h * n.w;
+  q[0] = -g * Ab * H - half * Ab * n.u * n.u + lam * T(1.0 / 6.0) * Ab * r * r - half * Bb * n.u * n.v -
+         half * Cb * n.u * n.w - a.h * n.u;
+  q[1] = -half * Ab * hu - half * Bb * hv - half * Cb * hw - a.h * n.h;
+  q[2] = half * Bb * hu;
+  q[3] = half * Cb * hu;
+  q[4] = lam * T(1.0 / 3.0) * Ab * omr - a.eta * n.u;
+  q[5] = lam * T(0.5) * Ab * omr - T(1.5) * a.eta * n.u;
+  q[6] = g * Ab;
+  q[7] = half * Ab * n.h;
+  q[8] = half * Ab * n.u;
+  q[9] = half * Bb;
+  q[10] = -lam * T(1.0 / 6.0) * Ab;
+  q[11] = half * Cb;
 }
 
-template <typename T, int BCX, int BCY>
-__device__ __forceinline__ Node<T> vjp_load(const T* __restrict__ Y, const T* __restrict__ bplane, size_t N, int nx,
-                                            int gi, int gj) {
-  const size_t o = (size_t)gj * nx + gi;
-  Node<T> n;
-  n.h = Y[o];
-  n.u = Y[N + o];
-  n.v = Y[2 * N + o];
-  n.w = Y[3 * N + o];
-  n.eta = Y[4 * N + o];
-  n.b = bplane[o];
-  n.ih = T(1) / n.h;
-  return n;
+// Same for the 12 y-quantities (h u v w eta b h(h+b) v^2 hv huv eta^2/h hvw).
+template <typename T>
+__device__ __forceinline__ void dbar_y(const Node<T>& n, const Seed<T>& a, T g, T lam, T (&q)[12]) {
+  const T half = T(0.5);
+  const T ih = n.ih;
+  const T Ab = -a.u * ih, Bb = -a.v * ih, Cb = -a.w * ih;
+  const T H = n.h + n.b, r = n.eta * ih, omr = T(1) - r;
+  const T hu = n.h * n.u, hv = n.h * n.v, hw = n.h * n.w;
+  q[0] = -g * Bb * H - half * Bb * n.v * n.v + lam * T(1.0 / 6.0) * Bb * r * r - half * Ab * n.u * n.v -
+         half * Cb * n.v * n.w - a.h * n.v;
+  q[1] = half * Ab * hv;
+  q[2] = -half * Bb * hv - half * Ab * hu - half * Cb * hw - a.h * n.h;
+  q[3] = half * Cb * hv;
+  q[4] = lam * T(1.0 / 3.0) * Bb * omr - a.eta * n.v;
+  q[5] = lam * T(0.5) * Bb * omr - T(1.5) * a.eta * n.v;
+  q[6] = g * Bb;
+  q[7] = half * Bb * n.h;
+  q[8] = half * Bb * n.v;
+  q[9] = half * Ab;
+  q[10] = -lam * T(1.0 / 6.0) * Bb;
+  q[11] = half * Cb;
 }
 
-// One reverse-mode stage (role ROLE) over the whole grid.  ROWS output rows per
-// wavefront work item.
-template <typename T, int BCX, int BCY, int ROLE, int ROWS>
-__global__ __launch_bounds__(64 * VJP_WAVES) void vjp_kernel(const GridConst gc, const T* __restrict__ Y,
-                                                             const T* __restrict__ bplane,
-                                                             const T* Kin, T* Qb,
-                                                             T* __restrict__ Kout, T* __restrict__ Acc,
-                                                             T* __restrict__ Bb, T a_in, T cq, T cy) {
+template <typename T, int TY>
+struct VjpSmem {
+  T f[12][TY + 2][TILE_X + 2];  // h u v w eta b 1/h | seeds of h u v w eta
+};
+
+template <typename T, int TY>
+__device__ __forceinline__ void vjp_lds(const VjpSmem<T, TY>& s, int r, int c, Node<T>& n, Seed<T>& a) {
+  n.h = s.f[0][r][c];
+  n.u = s.f[1][r][c];
+  n.v = s.f[2][r][c];
+  n.w = s.f[3][r][c];
+  n.eta = s.f[4][r][c];
+  n.b = s.f[5][r][c];
+  n.ih = s.f[6][r][c];
+  a.h = s.f[7][r][c];
+  a.u = s.f[8][r][c];
+  a.v = s.f[9][r][c];
+  a.w = s.f[10][r][c];
+  a.eta = s.f[11][r][c];
+}
+
+// One reverse-mode stage (role ROLE) on a 64 x TY tile per workgroup.
+template <typename T, int BCX, int BCY, int ROLE, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, const T* __restrict__ Y,
+                                                            const T* __restrict__ bplane, const T* Kin, T* Qb,
+                                                            T* __restrict__ Kout, T* __restrict__ Acc,
+                                                            T* __restrict__ Bb, T a_in, T cq, T cy) {
+  static_assert(TY % THREAD_ROWS == 0, "tile height must be a multiple of 4");
+  constexpr int RPT = TY / THREAD_ROWS;
+  constexpr int W = TILE_X + 2;
+  constexpr int REGION = (TY + 2) * W;
+  __shared__ VjpSmem<T, TY> s;
   const int nx = gc.nx, ny = gc.ny;
   const size_t N = (size_t)nx * (size_t)ny;
-  const int lane = threadIdx.x & 63;
-  const int nsx = (nx + VJP_STRIP - 1) / VJP_STRIP;
-  const int nsy = (ny + ROWS - 1) / ROWS;
-  const int item = blockIdx.x * VJP_WAVES + (threadIdx.x >> 6);
-  if (item >= nsx * nsy) return;  // whole wavefront leaves together
-  const int sxi = item % nsx, syi = item / nsx;
-  const int c0 = sxi * VJP_STRIP;
-  const int jstart = syi * ROWS;
-  const int jend = min(jstart + ROWS, ny);
+  const int ntx = (nx + TILE_X - 1) / TILE_X;
+  const int nty = (ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  const int i0 = (tile % ntx) * TILE_X;
+  const int j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+  const int tx = tid & (TILE_X - 1);
+  const int ty = tid >> 6;
 
-  const int col = c0 - 2 + lane;  // unwrapped column of this lane
-  const bool col_in = BCX == BC_PERIODIC || (col >= 0 && col < nx);
-  const int gi = vjp_wrap<BCX>(col, nx);
-  const bool reverse_lane = lane >= 1 && lane <= 62 && col_in;
-  const bool out_lane = lane >= 2 && lane <= 61 && col >= c0 && col < c0 + VJP_STRIP && col < nx;
-  // x stencil of this lane's node
-  int omx = -1, opx = 1;
-  T sx = T(gc.inv2dx), satx = T(0);
-  if (BCX == BC_REFLECTING) {
-    if (col == 0) {
-      omx = 0;
-      sx = T(gc.invdx);
-      satx = T(-2.0 * gc.invdx);
+  for (int idx = tid; idx < REGION; idx += STAGE_THREADS) {
+    const int rr = idx / W;
+    const int cc = idx - rr * W;
+    int gi = i0 - 1 + cc;
+    int gj = j0 - 1 + rr;
+    if (BCX == BC_PERIODIC) {
+      if (gi < 0) gi += nx;
+      while (gi >= nx) gi -= nx;
+    } else {
+      gi = gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi);
     }
-    if (col == nx - 1) {
-      opx = 0;
-      sx = T(gc.invdx);
-      satx = T(2.0 * gc.invdx);
+    if (BCY == BC_PERIODIC) {
+      if (gj < 0) gj += ny;
+      while (gj >= ny) gj -= ny;
+    } else {
+      gj = gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj);
     }
+    const size_t o = (size_t)gj * nx + gi;
+    const T h = Y[o];
+    s.f[0][rr][cc] = h;
+    s.f[1][rr][cc] = Y[N + o];
+    s.f[2][rr][cc] = Y[2 * N + o];
+    s.f[3][rr][cc] = Y[3 * N + o];
+    s.f[4][rr][cc] = Y[4 * N + o];
+    s.f[5][rr][cc] = bplane[o];
+    s.f[6][rr][cc] = T(1) / h;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = a_in * Kin[f * N + o];
   }
+  __syncthreads();
+
   const T g = T(gc.g), lam = T(gc.lam);
-
-  // rolling window of raw rows j-1, j, j+1 (and j+2 in flight) and partial
-  // cotangents of rows j-1, j; the rate cotangents of row j+1 are also fetched
-  // one row ahead, so every load has a row of work to hide behind.
-  Node<T> Rm = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart - 2, ny));
-  Node<T> R0 = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart - 1, ny));
-  Node<T> Rn = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(jstart, ny));
-  T kbn[5];
-  {
-    const int j = jstart - 1;
-    const bool row_in = BCY == BC_PERIODIC || (j >= 0 && j < ny);
-    const size_t o = (size_t)vjp_wrap<BCY>(j, ny) * nx + gi;
-#pragma unroll
-    for (int f = 0; f < 5; ++f) kbn[f] = (reverse_lane && row_in) ? a_in * Kin[f * N + o] : T(0);
+  const int i = i0 + tx;
+  const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
+  const AxisTranspose<T, BCX> tx_(i, nx, gc.inv2dx, gc.invdx);
+  T satx = T(0);
+  if (BCX == BC_REFLECTING) {
+    if (i == 0) satx = T(-2.0 * gc.invdx);
+    if (i == nx - 1) satx = T(2.0 * gc.invdx);
   }
-  Cot<T> Pm, P0;
-  Pm.zero();
-  P0.zero();
 
-  for (int j = jstart - 1; j <= jend; ++j) {
-    const Node<T> Rp = Rn;
-    T kb[5];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) kb[f] = kbn[f];
-    if (j + 1 <= jend) {
-      Rn = vjp_load<T, BCX, BCY>(Y, bplane, N, nx, gi, vjp_wrap<BCY>(j + 2, ny));
-      const bool nrow_in = BCY == BC_PERIODIC || (j + 1 >= 0 && j + 1 < ny);
-      const size_t o = (size_t)vjp_wrap<BCY>(j + 1, ny) * nx + gi;
-#pragma unroll
-      for (int f = 0; f < 5; ++f) kbn[f] = (reverse_lane && nrow_in) ? a_in * Kin[f * N + o] : T(0);
+  for (int k = 0; k < RPT; ++k) {
+    const int lr = ty + k * THREAD_ROWS;
+    const int j = j0 + lr;
+    if (i >= nx || j >= ny) continue;
+    const AxisStencil<BCY> ay(j, ny, gc.inv2dy, gc.invdy);
+    const AxisTranspose<T, BCY> ty_(j, ny, gc.inv2dy, gc.invdy);
+    T saty = T(0);
+    if (BCY == BC_REFLECTING) {
+      if (j == 0) saty = T(-2.0 * gc.invdy);
+      if (j == ny - 1) saty = T(2.0 * gc.invdy);
     }
-    const bool row_in = BCY == BC_PERIODIC || (j >= 0 && j < ny);
-    // x neighbours of this row (all lanes take part in the shuffles)
-    const Node<T> XM = shfl_node_left(R0);
-    const Node<T> XP = shfl_node_right(R0);
-    Cot<T> cen, sendL, sendR, toUp, toDown;
-    cen.zero();
-    sendL.zero();
-    sendR.zero();
-    toUp.zero();
-    toDown.zero();
-    if (reverse_lane && row_in) {
-      int omy = -1, opy = 1;
-      T sy = T(gc.inv2dy), saty = T(0);
-      if (BCY == BC_REFLECTING) {
-        if (j == 0) {
-          omy = 0;
-          sy = T(gc.invdy);
-          saty = T(-2.0 * gc.invdy);
+    const int r = lr + 1, c = tx + 1;
+    Node<T> nc, nxm, nxp, nym, nyp;
+    Seed<T> ac, axm, axp, aym, ayp;
+    vjp_lds(s, r, c, nc, ac);
+    vjp_lds(s, r, c - 1, nxm, axm);
+    vjp_lds(s, r, c + 1, nxp, axp);
+    vjp_lds(s, r - 1, c, nym, aym);
+    vjp_lds(s, r + 1, c, nyp, ayp);
+    // local part: reverse of this node's own rates (stencil neighbours with closures)
+    const Node<T>& sxm = ax.om == 0 ? nc : nxm;
+    const Node<T>& sxp = ax.op == 0 ? nc : nxp;
+    const Node<T>& sym = ay.om == 0 ? nc : nym;
+    const Node<T>& syp = ay.op == 0 ? nc : nyp;
+    const T kb[5] = {ac.h, ac.u, ac.v, ac.w, ac.eta};
+    Cot<T> out;
+    T dX[12], dY[12];
+    split_form_reverse<T>(nc, sxm, sxp, sym, syp, T(ax.scale), T(ay.scale), g, lam, satx, saty, kb, out, dX, dY);
+    // transpose part: Dbar of the neighbours (and of this node on closure columns)
+    T qa[12], qb[12], amt[12];
+    dbar_x(nxm, axm, g, lam, qa);
+    dbar_x(nxp, axp, g, lam, qb);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) amt[m] = tx_.wl * qa[m] + tx_.wc * dX[m] + tx_.wr * qb[m];
+    out.add(chain_x(nc, amt));
+    dbar_y(nym, aym, g, lam, qa);
+    dbar_y(nyp, ayp, g, lam, qb);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) amt[m] = ty_.wl * qa[m] + ty_.wc * dY[m] + ty_.wr * qb[m];
+    out.add(chain_y(nc, amt));
+
+    const size_t od = (size_t)j * nx + i;
+    const T yb[5] = {out.h, out.u, out.v, out.w, out.eta};
+    if (ROLE == VJP_PLAIN) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) Kout[f * N + od] = yb[f];
+      Bb[od] = out.b;
+    } else {
+      if (ROLE == VJP_S4) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          const T q = Qb[f * N + od];
+          Kout[f * N + od] = cq * q + cy * yb[f];
+          Acc[f * N + od] = yb[f];
         }
-        if (j == ny - 1) {
-          opy = 0;
-          sy = T(gc.invdy);
-          saty = T(2.0 * gc.invdy);
+      } else if (ROLE == VJP_S3 || ROLE == VJP_S2) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          const T q = Qb[f * N + od];
+          Kout[f * N + od] = cq * q + cy * yb[f];
+          Acc[f * N + od] = Acc[f * N + od] + yb[f];
         }
-      }
-      const Node<T>& xm = omx == 0 ? R0 : XM;
-      const Node<T>& xp = opx == 0 ? R0 : XP;
-      const Node<T>& ym = omy == 0 ? R0 : Rm;
-      const Node<T>& yp = opy == 0 ? R0 : Rp;
-      T dX[12], dY[12];
-      split_form_reverse<T>(R0, xm, xp, ym, yp, sx, sy, g, lam, satx, saty, kb, cen, dX, dY);
-      T ax[12], ay[12];
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        ax[k] = sx * dX[k];
-        ay[k] = sy * dY[k];
-      }
-      const Cot<T> cxp = chain_x(xp, ax);  // +s Dbar to the right target
-      const Cot<T> cyp = chain_y(yp, ay);
-#pragma unroll
-      for (int k = 0; k < 12; ++k) {
-        ax[k] = -ax[k];
-        ay[k] = -ay[k];
-      }
-      const Cot<T> cxm = chain_x(xm, ax);  // -s Dbar to the left target
-      const Cot<T> cym = chain_y(ym, ay);
-      if (opx == 0) cen.add(cxp); else sendR = cxp;
-      if (omx == 0) cen.add(cxm); else sendL = cxm;
-      if (opy == 0) cen.add(cyp); else toDown = cyp;
-      if (omy == 0) cen.add(cym); else toUp = cym;
-    }
-    // what the neighbours in this row send to this lane
-    Cot<T> recv;
-    recv.h = shfl_from_left(sendR.h) + shfl_from_right(sendL.h);
-    recv.u = shfl_from_left(sendR.u) + shfl_from_right(sendL.u);
-    recv.v = shfl_from_left(sendR.v) + shfl_from_right(sendL.v);
-    recv.w = shfl_from_left(sendR.w) + shfl_from_right(sendL.w);
-    recv.eta = shfl_from_left(sendR.eta) + shfl_from_right(sendL.eta);
-    recv.b = shfl_from_left(sendR.b) + shfl_from_right(sendL.b);
-    P0.add(cen);
-    P0.add(recv);
-    Pm.add(toUp);
-    // row j-1 is complete
-    const int jd = j - 1;
-    if (out_lane && jd >= jstart && jd < jend) {
-      const size_t od = (size_t)jd * nx + col;
-      const T yb[5] = {Pm.h, Pm.u, Pm.v, Pm.w, Pm.eta};
-      if (ROLE == VJP_PLAIN) {
-#pragma unroll
-        for (int f = 0; f < 5; ++f) Kout[f * N + od] = yb[f];
-        Bb[od] = Pm.b;
       } else {
-        if (ROLE == VJP_S4) {
 #pragma unroll
-          for (int f = 0; f < 5; ++f) {
-            const T qb = Qb[f * N + od];
-            Kout[f * N + od] = cq * qb + cy * yb[f];
-            Acc[f * N + od] = yb[f];
-          }
-        } else if (ROLE == VJP_S3 || ROLE == VJP_S2) {
-#pragma unroll
-          for (int f = 0; f < 5; ++f) {
-            const T qb = Qb[f * N + od];
-            Kout[f * N + od] = cq * qb + cy * yb[f];
-            Acc[f * N + od] = Acc[f * N + od] + yb[f];
-          }
-        } else {
-#pragma unroll
-          for (int f = 0; f < 5; ++f) Qb[f * N + od] = Qb[f * N + od] + Acc[f * N + od] + yb[f];
-        }
-        Bb[od] = Bb[od] + Pm.b;
+        for (int f = 0; f < 5; ++f) Qb[f * N + od] = Qb[f * N + od] + Acc[f * N + od] + yb[f];
       }
+      Bb[od] = Bb[od] + out.b;
     }
-    Pm = P0;
-    P0 = toDown;
-    Rm = R0;
-    R0 = Rp;
   }
 }
 
