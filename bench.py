@@ -39,8 +39,12 @@ HBM_PEAK_GBS = 8000.0
 #  stages: stage 1 reads q, b and writes acc, Y (16); stages 2 and 3 read Y, b,
 #          q, acc and write acc, Y (26 each); stage 4 reads Y, b, acc and writes
 #          q (16)                 -> 84 values, 4 launches
-PATHS = {"pairs": (37, 2), "stages": (84, 4)}
-ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "stages"}
+#  fused:  the step kernel reads q, b and writes q_new -> 11 values, 1 launch
+PATHS = {"pairs": (37, 2), "stages": (84, 4), "fused": (11, 1)}
+KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
+           "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
+           "fused": "step_kernel (one whole RK4 step per launch)"}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths"}
 
 
 def log(msg):
@@ -114,6 +118,7 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
         "path": path,
         "tile_y": tile_y,
         "kernel_ms": ({"pair1": ms[0], "pair2": ms[1]} if path == "pairs" else
+                      {"step": ms[0]} if path == "fused" else
                       {"stage1": ms[0], "stage2": ms[1], "stage3": ms[2], "stage4": ms[3]}),
         "mass_drift_rel": (m1 - m0) / abs(m0),
         "energy_drift_rel": (e1 - e0) / abs(e0),
@@ -274,7 +279,7 @@ def main():
     ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
-                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,stages (default all)")
+                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths (default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
@@ -324,10 +329,11 @@ def main():
         variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
-    if "stages" in chosen:
-        other = "stages" if P == "pairs" else "pairs"
-        variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
-                                                    f"periodic f64 {other}", other, T)
+    if "paths" in chosen:
+        for other in sorted(PATHS):
+            if other != P:
+                variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
+                                                            f"periodic f64 {other}", other, T)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -355,8 +361,7 @@ def main():
                    "dt": main_res["dt"], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": main_res["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": main_res["frac"], "traffic": None,
-                     "kernel": (f"pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)" if P == "pairs"
-                                else "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)"),
+                     "kernel": KERNELS[P],
                      "algorithmic_bytes_per_launch_per_node": PATHS[P][0] / PATHS[P][1] * 8,
                      "algorithmic_bytes_per_step_per_node": PATHS[P][0] * 8},
         "cpu_baseline": cpu,

@@ -93,10 +93,14 @@ typedef struct sgn_ctx sgn_ctx;
  *     intermediate stage stays in LDS.  37 values of HBM traffic per node and
  *     step.  An odd final step runs on the four-stage path.
  *   SGN_PATH_STAGES: four kernels, one per stage.  84 values per node and step.
+ *   SGN_PATH_FUSED: one kernel per step; the three intermediate stages stay in
+ *     LDS (a four-node halo, evaluated redundantly in rings around each tile).
+ *     11 values per node and step.  An odd final step runs on the four-stage path.
  * SGN_OPT_TILE_Y: tile height of the stage and pair kernels, 8 or 16 (default 8 for
- *   SGN_F64, 16 for SGN_F32). */
+ *   SGN_F64, 16 for SGN_F32).  On the fused path the tile holds 512 nodes:
+ *   8 selects 64 x 8, 16 selects 32 x 16. */
 typedef enum { SGN_OPT_STEP_PATH = 0, SGN_OPT_TILE_Y = 1 } sgn_option;
-typedef enum { SGN_PATH_PAIRS = 0, SGN_PATH_STAGES = 1 } sgn_step_path;
+typedef enum { SGN_PATH_PAIRS = 0, SGN_PATH_STAGES = 1, SGN_PATH_FUSED = 2 } sgn_step_path;
 
 /* Create a context on the current HIP device.  stream is a hipStream_t (NULL
  * for the null stream).  Allocates the Runge-Kutta scratch (three states), a
@@ -152,7 +156,8 @@ sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
  * launches, recording HIP events on the context's stream around every kernel.
  * Four-stage path: ms[s] = mean duration of stage kernel s (0 = first, 1 and 2
  * = middle, 3 = last).  Pair path: ms[0] = pair 1, ms[1] = pair 2, ms[2] =
- * ms[3] = 0 (an odd nsteps is rounded up).  Milliseconds; synchronizes. */
+ * ms[3] = 0.  Fused path: ms[0] = the step kernel, ms[1..3] = 0.  On the pair
+ * and fused paths an odd nsteps is rounded up.  Milliseconds; synchronizes. */
 sgn_status sgn_profile_stages(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* ms);
 
 /* Synchronize and report (then clear) the device health flag. */

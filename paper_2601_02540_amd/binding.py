@@ -21,7 +21,7 @@ HEADER_PATH = os.path.join(ROOT, "include", "sgn.h")
 SGN_F64, SGN_F32 = 0, 1
 SGN_SRC_NONE, SGN_SRC_MMS = 0, 1
 SGN_OPT_STEP_PATH, SGN_OPT_TILE_Y = 0, 1
-SGN_PATH_PAIRS, SGN_PATH_STAGES = 0, 1
+SGN_PATH_PAIRS, SGN_PATH_STAGES, SGN_PATH_FUSED = 0, 1, 2
 
 
 class SgnError(RuntimeError):
@@ -189,8 +189,10 @@ class Solver:
         self._chk(self.lib.sgn_set_option(self.ctx, int(option), int(value)))
 
     def set_step_path(self, path: str):
-        """'pairs' (two fused stage pairs per step, default) or 'stages' (four stage kernels)."""
-        self.set_option(SGN_OPT_STEP_PATH, {"pairs": SGN_PATH_PAIRS, "stages": SGN_PATH_STAGES}[path])
+        """'pairs' (two fused stage pairs per step, default), 'stages' (four stage kernels) or
+        'fused' (one kernel per step)."""
+        self.set_option(SGN_OPT_STEP_PATH,
+                        {"pairs": SGN_PATH_PAIRS, "stages": SGN_PATH_STAGES, "fused": SGN_PATH_FUSED}[path])
 
     def set_tile_y(self, ty: int):
         self.set_option(SGN_OPT_TILE_Y, ty)
@@ -239,7 +241,8 @@ class Solver:
         return dt.value
 
     def profile_stages(self, q, dt: float, nsteps: int):
-        """Mean duration (ms) of each of the four stage kernels over nsteps steps."""
+        """Mean kernel durations (ms) over nsteps steps: the four stage kernels, the two
+        pair kernels (then two zeros) or the step kernel (then three zeros)."""
         ms = (ctypes.c_double * 4)()
         self._chk(self.lib.sgn_profile_stages(self.ctx, self._state(q), float(dt), int(nsteps), ms))
         return list(ms)

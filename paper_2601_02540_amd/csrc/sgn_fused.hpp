@@ -1,0 +1,257 @@
+// sgn_fused.hpp -- one classical RK4 step in one kernel.
+//
+// Each workgroup owns a tile of TX x TY = 512 nodes and stages the state q with
+// a four-node halo of (h, u, v, w, eta, b, 1/h) in LDS.  The four right-hand
+// sides of the step are evaluated on shrinking regions, since each evaluation
+// reaches one node further than the stage it reads:
+//   k1 = f(q)   on the tile and the rings at distance 1..3,  Y2 = q + dt/2 k1
+//   k2 = f(Y2)  on the tile and the rings at distance 1..2,  Y3 = q + dt/2 k2
+//   k3 = f(Y3)  on the tile and the ring at distance 1,      Y4 = q + dt k3
+//   k4 = f(Y4)  on the tile:  q_new = acc + dt/6 k4,
+// with acc = q + dt/6 k1 + dt/3 k2 + dt/3 k3 kept in registers for the owned
+// nodes.  Each intermediate stage overwrites the previous one in LDS (b is
+// kept).  Only q and b are read and q_new written: 11 values per node and
+// step from HBM, against 37 for the two pair kernels and 84 for four stage
+// kernels.  The price is the ring evaluations (48 wave evaluations per tile and
+// step for a 64 x 8 tile, 44 for 32 x 16, against 32 without rings).
+//
+// Thread map: thread t owns the tile nodes t and t + 256 (row-major in the
+// tile) in every stage, so their q and acc stay in registers.  Ring nodes are
+// numbered by distance (all of ring 1 first, then ring 2, then ring 3); thread
+// t evaluates ring nodes t and t + 256 in every stage whose region contains
+// them, so the q of a ring node is read from LDS once, in the first stage.
+//
+// The output buffer must not alias the input (neighbouring tiles read the
+// halo of q); sgn_step alternates between the caller's buffer and the
+// context's accumulator buffer.
+#pragma once
+
+#include "sgn_pair.hpp"
+
+namespace sgn {
+
+constexpr int STEP_NODES = 512;  // owned nodes per tile (two per thread)
+constexpr int STEP_HALO = 4;     // one node per right-hand side of the step
+
+template <int TX>
+struct StepGeom {
+  static constexpr int TY = STEP_NODES / TX;
+  static constexpr int RX = TX + 2 * STEP_HALO;
+  static constexpr int RY = TY + 2 * STEP_HALO;
+  static constexpr int ROWS = STAGE_THREADS / TX;  // tile rows covered by one pass of the threads
+  // nodes of the ring at distance d around the tile
+  static constexpr int ring(int d) { return 2 * (TX + 2 * d) + 2 * (TY + 2 * d - 2); }
+  static constexpr int RING1 = ring(1);
+  static constexpr int RING2 = RING1 + ring(2);
+  static constexpr int RING3 = RING2 + ring(3);
+  static_assert(STEP_NODES % TX == 0 && STAGE_THREADS % TX == 0, "tile width must divide 256");
+  static_assert(RING3 <= 2 * STAGE_THREADS, "two ring slots per thread");
+};
+
+template <typename T, int TX>
+struct StepSmem {
+  T f[7][StepGeom<TX>::RY][StepGeom<TX>::RX];  // h u v w eta b 1/h, then the current stage (b kept)
+};
+
+// Position (r, c), relative to the tile origin, of ring node m (0 <= m < RING3).
+template <int TX>
+__device__ __forceinline__ void ring_node(int m, int& r, int& c) {
+  using G = StepGeom<TX>;
+  int d;
+  if (m < G::RING1) {
+    d = 1;
+  } else if (m < G::RING2) {
+    d = 2;
+    m -= G::RING1;
+  } else {
+    d = 3;
+    m -= G::RING2;
+  }
+  const int w = TX + 2 * d;          // top and bottom rows
+  const int hs = G::TY + 2 * d - 2;  // left and right columns without the corners
+  if (m < w) {
+    r = -d;
+    c = m - d;
+  } else if (m < 2 * w) {
+    r = G::TY - 1 + d;
+    c = m - w - d;
+  } else if (m < 2 * w + hs) {
+    r = m - 2 * w - d + 1;
+    c = -d;
+  } else {
+    r = m - 2 * w - hs - d + 1;
+    c = TX - 1 + d;
+  }
+}
+
+template <typename T, int BCX, int BCY, bool SRC, int TX>
+__global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
+                                                             const T* __restrict__ bplane, T* __restrict__ qout,
+                                                             T c6, T c3, T c2, T c1, double t0, double dt,
+                                                             int* __restrict__ flag) {
+  using G = StepGeom<TX>;
+  constexpr int TY = G::TY;
+  constexpr int RX = G::RX;
+  constexpr int REGION = G::RX * G::RY;
+  __shared__ StepSmem<T, TX> s;
+
+  const int nx = gc.nx, ny = gc.ny;
+  const size_t N = (size_t)nx * (size_t)ny;
+  const int ntx = (nx + TX - 1) / TX;
+  const int nty = (ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  const int i0 = (tile % ntx) * TX;
+  const int j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+
+  // 1. Stage q and b with the four-node halo (periodic wrap or wall clamp).
+  //    Every load of the region is issued before the first one is waited
+  //    for: the step kernel reads little per unit of work, so its bandwidth
+  //    is set by how many bytes each workgroup keeps in flight.
+  {
+    constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
+    T v[ITER][6];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGION) {
+        const int rr = idx / RX;
+        const int cc = idx - rr * RX;
+        const int gi = wrap_or_clamp<BCX>(i0 - STEP_HALO + cc, nx);
+        const int gj = wrap_or_clamp<BCY>(j0 - STEP_HALO + rr, ny);
+        const size_t o = (size_t)gj * nx + gi;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[it][f] = q[f * N + o];
+        v[it][5] = bplane[o];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGION) {
+        const int rr = idx / RX;
+        const int cc = idx - rr * RX;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
+        s.f[6][rr][cc] = T(1) / v[it][0];
+      }
+    }
+  }
+
+  // Owned nodes (lx, ly[k]) and ring slots of this thread.
+  const int lx = tid % TX;
+  const int ly0 = tid / TX;
+  const int i = i0 + lx;
+  bool own_dom[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int j = j0 + ly0 + k * G::ROWS;
+    own_dom[k] = on_axis<BCX>(i, nx) && on_axis<BCY>(j, ny);
+  }
+  int ring_r[2], ring_c[2];
+  bool ring_ok[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int m = tid + k * STAGE_THREADS;
+    ring_r[k] = 0;
+    ring_c[k] = 0;
+    ring_ok[k] = false;
+    if (m < G::RING3) {
+      ring_node<TX>(m, ring_r[k], ring_c[k]);
+      ring_ok[k] = on_axis<BCX>(i0 + ring_c[k], nx) && on_axis<BCY>(j0 + ring_r[k], ny);
+    }
+  }
+  __syncthreads();
+
+  T qo[2][5], acc[2][5], qr[2][5];
+  int health = 0;
+#pragma unroll
+  for (int st = 1; st <= 4; ++st) {
+    const T cy = st == 3 ? c1 : c2;     // Y_{st+1} = q + cy k_st
+    const T ca = st == 1 || st == 4 ? c6 : c3;  // acc += ca k_st
+    const double ts = t0 + (st == 1 ? 0.0 : (st == 4 ? dt : 0.5 * dt));
+    const int ring_lim = st == 1 ? G::RING3 : (st == 2 ? G::RING2 : G::RING1);
+    T ro[2][5], rr[2][5];
+    // owned nodes
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int ly = ly0 + k * G::ROWS;
+      const int j = j0 + ly;
+      if (st < 4 ? !own_dom[k] : (i >= nx || j >= ny)) continue;
+      Node<T> cn;
+      const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ly + STEP_HALO, lx + STEP_HALO, i, j, gc, ts, cn);
+      const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
+      if (st == 1) {
+        const T yv[5] = {cn.h, cn.u, cn.v, cn.w, cn.eta};
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          qo[k][f] = yv[f];
+          acc[k][f] = yv[f] + ca * kv[f];
+          ro[k][f] = yv[f] + cy * kv[f];
+        }
+      } else if (st < 4) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          acc[k][f] = acc[k][f] + ca * kv[f];
+          ro[k][f] = qo[k][f] + cy * kv[f];
+        }
+      } else {
+        const size_t o = (size_t)j * nx + i;
+        T nv[5];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) {
+          nv[f] = acc[k][f] + ca * kv[f];
+          qout[f * N + o] = nv[f];
+        }
+        if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
+        const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
+        if (!isfinite(sum)) health |= FLAG_NONFINITE;
+      }
+    }
+    if (st == 4) break;
+    // ring nodes inside this stage's region
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      __builtin_amdgcn_sched_barrier(0);
+      const int m = tid + k * STAGE_THREADS;
+      if (m >= ring_lim || !ring_ok[k]) continue;
+      Node<T> cn;
+      const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ring_r[k] + STEP_HALO, ring_c[k] + STEP_HALO,
+                                                      i0 + ring_c[k], j0 + ring_r[k], gc, ts, cn);
+      const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
+      if (st == 1) {
+        qr[k][0] = cn.h;
+        qr[k][1] = cn.u;
+        qr[k][2] = cn.v;
+        qr[k][3] = cn.w;
+        qr[k][4] = cn.eta;
+      }
+#pragma unroll
+      for (int f = 0; f < 5; ++f) rr[k][f] = qr[k][f] + cy * kv[f];
+    }
+    __syncthreads();
+    // the stage just formed replaces the one read
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      if (!own_dom[k]) continue;
+      const int r = ly0 + k * G::ROWS + STEP_HALO, c = lx + STEP_HALO;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.f[f][r][c] = ro[k][f];
+      s.f[6][r][c] = T(1) / ro[k][0];
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int m = tid + k * STAGE_THREADS;
+      if (m >= ring_lim || !ring_ok[k]) continue;
+      const int r = ring_r[k] + STEP_HALO, c = ring_c[k] + STEP_HALO;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.f[f][r][c] = rr[k][f];
+      s.f[6][r][c] = T(1) / rr[k][0];
+    }
+    __syncthreads();
+  }
+  if (health) atomicOr(flag, health);
+}
+
+}  // namespace sgn

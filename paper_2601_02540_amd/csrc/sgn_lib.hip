@@ -9,6 +9,7 @@
 #include "sgn.h"
 #include "sgn_internal.hpp"
 #include "sgn_reduce.hpp"
+#include "sgn_fused.hpp"
 #include "sgn_pair.hpp"
 #include "sgn_stage.hpp"
 
@@ -146,6 +147,52 @@ hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const v
   return launch_pair_ty<float, PAIR, 8>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
 }
 
+template <typename T, int TX>
+hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0) {
+  constexpr int TY = sgn::STEP_NODES / TX;
+  const int ntx = (c->p.nx + TX - 1) / TX;
+  const int nty = (c->p.ny + TY - 1) / TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
+  const bool src = c->p.source == SGN_SRC_MMS;
+  const T* qp = (const T*)qin;
+  const T* bp = (const T*)c->b;
+  T* op = (T*)qout;
+#define SGN_LAUNCH(BX, BY, S)                                                                                  \
+  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX>), grid, block, 0, s, c->gc, qp, bp, op, (T)(dt / 6.0), \
+                     (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (!src) {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, false);
+    else SGN_LAUNCH(1, 1, false);
+  } else {
+    if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, true);
+    else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, true);
+    else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, true);
+    else SGN_LAUNCH(1, 1, true);
+  }
+#undef SGN_LAUNCH
+  return hipGetLastError();
+}
+
+// One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct).
+hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0) {
+  if (c->p.dtype == SGN_F64) {
+    if (c->tile_y == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0);
+    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0);
+  }
+  if (c->tile_y == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0);
+  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0);
+}
+
+// Two RK4 steps on the fused path: q -> acc -> q.
+hipError_t enqueue_fused_double_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, double t) {
+  hipError_t e = launch_fused(c, s, q, c->acc, dt, t);
+  if (e) return e;
+  return launch_fused(c, s, c->acc, q, dt, t + dt);
+}
+
 // One RK4 step with two fused stage pairs, from state buffer `cur` into `oth`
 // (which also carries acc between the two launches).
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {
@@ -174,12 +221,20 @@ hipError_t enqueue_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, dou
   return launch_stage<sgn::MODE_LAST>(c, s, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
 }
 
+// Two RK4 steps that leave the state in q, on the pair or the fused path.
+hipError_t enqueue_double_step(const sgn_ctx* c, hipStream_t s, void* q, double dt, double t) {
+  if (c->step_path == SGN_PATH_FUSED) return enqueue_fused_double_step(c, s, q, dt, t);
+  return enqueue_pair_double_step(c, s, q, dt, t);
+}
+
+bool double_steps(const sgn_ctx* c) { return c->step_path == SGN_PATH_PAIRS || c->step_path == SGN_PATH_FUSED; }
+
 // Enqueues `steps` RK4 steps on the context's step path (an even count on the
-// pair path).
+// pair and fused paths).
 hipError_t enqueue_steps(const sgn_ctx* c, hipStream_t s, void* q, double dt, int steps, double t0) {
   hipError_t e = hipSuccess;
-  if (c->step_path == SGN_PATH_PAIRS) {
-    for (int k = 0; k + 1 < steps && e == hipSuccess; k += 2) e = enqueue_pair_double_step(c, s, q, dt, t0 + k * dt);
+  if (double_steps(c)) {
+    for (int k = 0; k + 1 < steps && e == hipSuccess; k += 2) e = enqueue_double_step(c, s, q, dt, t0 + k * dt);
   } else {
     for (int k = 0; k < steps && e == hipSuccess; ++k) e = enqueue_step(c, s, q, dt, t0 + k * dt);
   }
@@ -444,8 +499,8 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
   if (c->p.source != SGN_SRC_NONE) {
     // Stage times matter: launch directly (pairs of steps, then a single one).
     int64_t s = 0;
-    if (c->step_path == SGN_PATH_PAIRS)
-      for (; s + 1 < nsteps; s += 2) HIPCHK(c, enqueue_pair_double_step(c, c->stream, q, dt, t0 + (double)s * dt));
+    if (double_steps(c))
+      for (; s + 1 < nsteps; s += 2) HIPCHK(c, enqueue_double_step(c, c->stream, q, dt, t0 + (double)s * dt));
     for (; s < nsteps; ++s) HIPCHK(c, enqueue_step(c, c->stream, q, dt, t0 + (double)s * dt));
     return SGN_OK;
   }
@@ -455,13 +510,13 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
     if ((st = get_graph(c, 0, q, dt, GRAPH_STEPS, &ge))) return st;
     for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS) HIPCHK(c, hipGraphLaunch(ge, c->stream));
   }
-  const int small = c->step_path == SGN_PATH_PAIRS ? 2 : 1;
+  const int small = double_steps(c) ? 2 : 1;
   if (left >= small) {
     hipGraphExec_t g1;
     if ((st = get_graph(c, 1, q, dt, small, &g1))) return st;
     for (; left >= small; left -= small) HIPCHK(c, hipGraphLaunch(g1, c->stream));
   }
-  // An odd final step on the pair path runs as four single-stage kernels in place.
+  // An odd final step on the pair or fused path runs as four single-stage kernels in place.
   if (left > 0) HIPCHK(c, enqueue_step(c, c->stream, q, dt, 0.0));
   return SGN_OK;
 }
@@ -469,7 +524,8 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
 sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
   if (!c) return SGN_E_ARG;
   if (option == SGN_OPT_STEP_PATH) {
-    if (value != SGN_PATH_PAIRS && value != SGN_PATH_STAGES) return fail(c, SGN_E_ARG, "unknown step path");
+    if (value != SGN_PATH_PAIRS && value != SGN_PATH_STAGES && value != SGN_PATH_FUSED)
+      return fail(c, SGN_E_ARG, "unknown step path");
     c->step_path = (int)value;
   } else if (option == SGN_OPT_TILE_Y) {
     if (value != 8 && value != 16) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
@@ -544,17 +600,24 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if (!q || !ms) return fail(c, SGN_E_ARG, "q or ms is NULL");
   if (!(std::isfinite(dt) && dt > 0.0) || nsteps <= 0) return fail(c, SGN_E_ARG, "dt must be > 0 and nsteps > 0");
   const bool pairs = c->step_path == SGN_PATH_PAIRS;
-  if (pairs && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
-  const int nk = pairs ? 4 : 4;         // launches recorded per profiled unit
+  const bool fused = c->step_path == SGN_PATH_FUSED;
+  if ((pairs || fused) && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
+  const int nk = fused ? 2 : 4;                      // launches recorded per profiled unit
   hipEvent_t ev[5];
   for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventCreate(&ev[k]));
   double acc_ms[4] = {0, 0, 0, 0};
   hipError_t e = hipSuccess;
-  const int64_t units = pairs ? nsteps / 2 : nsteps;
+  const int64_t units = (pairs || fused) ? nsteps / 2 : nsteps;
   for (int64_t u = 0; u < units && e == hipSuccess; ++u) {
-    const double t = (double)u * (pairs ? 2.0 : 1.0) * dt;
+    const double t = (double)u * ((pairs || fused) ? 2.0 : 1.0) * dt;
     e = hipEventRecord(ev[0], c->stream);
-    if (pairs) {
+    if (fused) {
+      // two consecutive steps (q -> acc -> q)
+      if (!e) e = launch_fused(c, c->stream, q, c->acc, dt, t);
+      if (!e) e = hipEventRecord(ev[1], c->stream);
+      if (!e) e = launch_fused(c, c->stream, c->acc, q, dt, t + dt);
+      if (!e) e = hipEventRecord(ev[2], c->stream);
+    } else if (pairs) {
       // pair 1 and pair 2 of two consecutive steps (q -> acc -> q)
       if (!e) e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
       if (!e) e = hipEventRecord(ev[1], c->stream);
@@ -572,8 +635,8 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
       if (!e) e = hipEventRecord(ev[3], c->stream);
       if (!e) e = launch_stage<sgn::MODE_LAST>(c, c->stream, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
     }
-    if (!e) e = hipEventRecord(ev[4], c->stream);
-    if (!e) e = hipEventSynchronize(ev[4]);
+    if (!e) e = hipEventRecord(ev[nk], c->stream);
+    if (!e) e = hipEventSynchronize(ev[nk]);
     for (int k = 0; k < nk && !e; ++k) {
       float m = 0.f;
       e = hipEventElapsedTime(&m, ev[k], ev[k + 1]);
@@ -582,7 +645,11 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   }
   for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
   if (e != hipSuccess) return hip_fail(c, e, "profiled step");
-  if (pairs) {
+  if (fused) {
+    // ms[0] = one fused step (mean over both steps of each unit)
+    ms[0] = (acc_ms[0] + acc_ms[1]) / (2.0 * (double)units);
+    ms[1] = ms[2] = ms[3] = 0.0;
+  } else if (pairs) {
     // ms[0] = pair 1, ms[1] = pair 2 (means over both steps of each unit)
     ms[0] = (acc_ms[0] + acc_ms[2]) / (2.0 * (double)units);
     ms[1] = (acc_ms[1] + acc_ms[3]) / (2.0 * (double)units);

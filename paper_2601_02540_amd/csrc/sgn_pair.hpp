@@ -47,9 +47,10 @@ __device__ __forceinline__ bool on_axis(int g, int n) {
 }
 
 // Right-hand side at LDS position (r, c) of node (i, j) (unwrapped indices).
-template <typename T, int BCX, int BCY, bool SRC, int TY>
-__device__ __forceinline__ Rates<T> pair_eval(const PairSmem<T, TY>& s, int r, int c, int i, int j, const GridConst& gc,
-                                              double t, Node<T>& center) {
+// `Smem` holds the planes h u v w eta b 1/h as f[7][rows][cols].
+template <typename T, int BCX, int BCY, bool SRC, class Smem>
+__device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i, int j, const GridConst& gc, double t,
+                                              Node<T>& center) {
   const AxisStencil<BCX> ax(i, gc.nx, gc.inv2dx, gc.invdx);
   const AxisStencil<BCY> ay(j, gc.ny, gc.inv2dy, gc.invdy);
   T satx = T(0), saty = T(0);
@@ -212,7 +213,7 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
     in_dom[k] = on_axis<BCX>(i, nx) && on_axis<BCY>(j, ny);
     if (!in_dom[k]) continue;
     Node<T> cnode;
-    const Rates<T> kk = pair_eval<T, BCX, BCY, SRC, TY>(s, lr + 2, tx + 2, i, j, gc, t1, cnode);
+    const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, lr + 2, tx + 2, i, j, gc, t1, cnode);
     const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
     if (PAIR == 1) {
       const T yv[5] = {cnode.h, cnode.u, cnode.v, cnode.w, cnode.eta};
@@ -234,7 +235,7 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
   __builtin_amdgcn_sched_barrier(0);
   if (ring_valid) {
     Node<T> cnode;
-    const Rates<T> kk = pair_eval<T, BCX, BCY, SRC, TY>(s, ring_r, ring_c, ring_i, ring_j, gc, t1, cnode);
+    const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ring_r, ring_c, ring_i, ring_j, gc, t1, cnode);
     const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
     const T yv[5] = {cnode.h, cnode.u, cnode.v, cnode.w, cnode.eta};
 #pragma unroll
@@ -272,7 +273,7 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
     const int j = j0 + lr;
     if (i >= nx || j >= ny) continue;
     Node<T> cnode;
-    const Rates<T> kk = pair_eval<T, BCX, BCY, SRC, TY>(s, lr + 2, tx + 2, i, j, gc, t2, cnode);
+    const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, lr + 2, tx + 2, i, j, gc, t2, cnode);
     const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
     const size_t o = (size_t)j * nx + i;
     if (PAIR == 1) {

@@ -244,9 +244,13 @@ def test_step_fp32_bounded_by_oracle_fp32():
 
 
 # ---------------------------------------------------------------------------
-# Step paths (two fused stage pairs per step, or four stage kernels) and tile heights
+# Step paths (two fused stage pairs per step, four stage kernels, or one fused
+# step kernel) and tile heights
 
-@pytest.mark.parametrize("shape", [(13, 11), (150, 37), (257, 70), (64, 64)])
+PATHS = ("pairs", "stages", "fused")
+
+
+@pytest.mark.parametrize("shape", [(4, 4), (5, 7), (13, 11), (150, 37), (257, 70), (64, 64)])
 @pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
 def test_step_paths_and_tiles(shape, bcs):
     nx, ny = shape
@@ -255,27 +259,27 @@ def test_step_paths_and_tiles(shape, bcs):
     q[1:4] *= 0.1
     dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
     ref3 = oracle.rk4(g, q, b, dt, 3)
-    for path in ("pairs", "stages"):
+    for path in PATHS:
         for ty in (8, 16):
             s = solver(g)
             s.set_step_path(path)
             s.set_tile_y(ty)
             s.set_bathymetry(dev(b))
             qd = dev(q)
-            s.step(qd, dt, 3)  # a double step then an odd single step on the pair path
+            s.step(qd, dt, 3)  # a double step then an odd single step on the pair and fused paths
             err = field_rel_err(host(qd), ref3, STATE_FLOORS)
             assert np.all(err <= F64_TOL), (path, ty, err)
 
 
 @pytest.mark.parametrize("bc", [PER, REF])
 def test_step_paths_mms_source(bc):
-    """Stage times reach the source correctly on both paths (direct launches)."""
+    """Stage times reach the source correctly on every path (direct launches)."""
     g = W.mms_grid(40, bc)
     p = W.mms_initial(g)
     q0 = oracle.init_aux(g, p.q0, p.b)
     dt = oracle.cfl_dt(g, q0, 0.5)
     ref = oracle.rk4(g, q0, p.b, dt, 5, 0.1, 1)
-    for path in ("pairs", "stages"):
+    for path in PATHS:
         s = solver(g, source=1)
         s.set_step_path(path)
         s.set_bathymetry(dev(p.b))
@@ -285,10 +289,10 @@ def test_step_paths_mms_source(bc):
         assert np.all(err <= F64_TOL), (path, err)
 
 
-def test_profile_stages_both_paths():
+def test_profile_stages_all_paths():
     p = W.gaussian_bump_periodic(256, seed=2)
     q0 = oracle.init_aux(p.grid, p.q0, p.b)
-    for path, nk in (("pairs", 2), ("stages", 4)):
+    for path, nk in (("pairs", 2), ("stages", 4), ("fused", 1)):
         s = solver(p.grid)
         s.set_step_path(path)
         s.set_bathymetry(dev(p.b))
@@ -297,3 +301,61 @@ def test_profile_stages_both_paths():
         assert all(m > 0 for m in ms[:nk]) and all(m == 0 for m in ms[nk:])
         ref = oracle.rk4(p.grid, q0, p.b, 0.01, 4)
         assert np.all(field_rel_err(host(qd), ref, STATE_FLOORS) <= F64_TOL)
+
+
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF)])
+def test_fused_path_long_run_matches_oracle(bcs):
+    """Many steps over a grid of many tiles with ragged tails: the fused step
+    kernel tracks the oracle like the other paths (even and odd step counts)."""
+    g = W.Grid(333, 141, -20.0, 20.0, -8.0, 9.0, bcs[0], bcs[1], 9.81, 500.0)
+    q, b = W.random_state(g, 77, b_scale=0.1)
+    q[1:4] *= 0.1
+    q = oracle.init_aux(g, q, b)
+    dt = oracle.cfl_dt(g, q, 0.5)
+    for n in (20, 21):
+        ref = oracle.rk4(g, q, b, dt, n)
+        for ty in (8, 16):
+            s = solver(g)
+            s.set_step_path("fused")
+            s.set_tile_y(ty)
+            s.set_bathymetry(dev(b))
+            qd = dev(q)
+            s.step(qd, dt, n)
+            s.check()
+            err = field_rel_err(host(qd), ref, STATE_FLOORS)
+            assert np.all(err <= F64_TOL), (n, ty, err)
+
+
+def test_fused_path_fp32_bounded_by_oracle_fp32():
+    p = W.gaussian_bump_periodic(64, seed=1)
+    g = p.grid
+    q0 = oracle.init_aux(g, p.q0, p.b).astype(np.float32).astype(np.float64)
+    dt = oracle.cfl_dt(g, q0, 0.5)
+    ref = oracle.rk4(g, q0, p.b, dt, 50)
+    bound = field_rel_err(oracle.rk4_f32(g, q0, p.b, dt, 50).astype(np.float64), ref, STATE_FLOORS)
+    for ty in (8, 16):
+        s = solver(g, torch.float32)
+        s.set_step_path("fused")
+        s.set_tile_y(ty)
+        s.set_bathymetry(dev(p.b, torch.float32))
+        qd = dev(q0, torch.float32)
+        s.step(qd, dt, 50)
+        err = field_rel_err(host(qd), ref, STATE_FLOORS)
+        assert np.all(err <= 4 * bound + 1e-6), (ty, err, bound)
+
+
+def test_fused_path_health_flag():
+    g = W.Grid(32, 16, 0.0, 1.0, 0.0, 1.0)
+    q = np.zeros((5, 16, 32))
+    q[0] = 1.0
+    q[4] = 1.0
+    q[0, 3, 5] = -0.5
+    s = solver(g)
+    s.set_step_path("fused")
+    s.set_bathymetry(dev(np.zeros((16, 32))))
+    qd = dev(q)
+    s.step(qd, 1e-6, 2)
+    from paper_2601_02540_amd.binding import SgnError
+    with pytest.raises(SgnError) as ei:
+        s.check()
+    assert ei.value.status == -5
