@@ -89,16 +89,19 @@ typedef struct sgn_ctx sgn_ctx;
 
 /* Options (sgn_set_option).
  * SGN_OPT_STEP_PATH: how sgn_step evaluates one RK4 step.
- *   SGN_PATH_PAIRS (default): two kernels, each fusing two stages; the
- *     intermediate stage stays in LDS.  37 values of HBM traffic per node and
- *     step.  An odd final step runs on the four-stage path.
+ *   SGN_PATH_FUSED (default): one kernel per step; the three intermediate
+ *     stages stay in LDS (a four-node halo, evaluated redundantly in rings
+ *     around each tile).  11 values of HBM traffic per node and step.
+ *   SGN_PATH_PAIRS: two kernels, each fusing two stages; the intermediate
+ *     stage stays in LDS.  37 values per node and step.
  *   SGN_PATH_STAGES: four kernels, one per stage.  84 values per node and step.
- *   SGN_PATH_FUSED: one kernel per step; the three intermediate stages stay in
- *     LDS (a four-node halo, evaluated redundantly in rings around each tile).
- *     11 values per node and step.  An odd final step runs on the four-stage path.
- * SGN_OPT_TILE_Y: tile height of the stage and pair kernels, 8 or 16 (default 8 for
- *   SGN_F64, 16 for SGN_F32).  On the fused path the tile holds 512 nodes:
- *   8 selects 64 x 8, 16 selects 32 x 16. */
+ *   On the fused and pair paths the state alternates between the caller's
+ *   buffer and a context buffer, so steps go in twos; an odd final step runs on
+ *   the four-stage path.
+ * SGN_OPT_TILE_Y: 8 or 16.  Tile height of the stage and pair kernels (64 wide;
+ *   default 8 for SGN_F64, 16 for SGN_F32) and shape of the step kernel's
+ *   512-node tile (8 selects 64 x 8, 16 selects 32 x 16; default 16).  Setting
+ *   the option sets both. */
 typedef enum { SGN_OPT_STEP_PATH = 0, SGN_OPT_TILE_Y = 1 } sgn_option;
 typedef enum { SGN_PATH_PAIRS = 0, SGN_PATH_STAGES = 1, SGN_PATH_FUSED = 2 } sgn_step_path;
 

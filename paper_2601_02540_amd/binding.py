@@ -189,8 +189,8 @@ class Solver:
         self._chk(self.lib.sgn_set_option(self.ctx, int(option), int(value)))
 
     def set_step_path(self, path: str):
-        """'pairs' (two fused stage pairs per step, default), 'stages' (four stage kernels) or
-        'fused' (one kernel per step)."""
+        """'fused' (one kernel per step, default), 'pairs' (two fused stage pairs per step) or
+        'stages' (four stage kernels)."""
         self.set_option(SGN_OPT_STEP_PATH,
                         {"pairs": SGN_PATH_PAIRS, "stages": SGN_PATH_STAGES, "fused": SGN_PATH_FUSED}[path])
 

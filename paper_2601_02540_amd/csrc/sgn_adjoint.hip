@@ -159,17 +159,24 @@ __global__ __launch_bounds__(256) void surface_to_state(const T* __restrict__ ze
 }
 
 // zeta = h + b at the gauges, one row of the series.  Also the misfit against a
-// target row and the loss increment (serial over the few gauges, so repeated
-// gauge nodes and the summation order are deterministic).
+// target row and the loss increment.  One block; thread t handles gauges t,
+// t + 256, ... and the loss increment is summed in a fixed tree order, so the
+// result is deterministic.
 // Gauge indices come from the caller: an index outside [0, N) is skipped and
 // raises FLAG_BADINDEX (reported as SGN_E_ARG by the next synchronizing call).
+constexpr int GAUGE_THREADS = 256;
+
 template <typename T>
-__global__ void gauge_record(const T* __restrict__ q, const T* __restrict__ b, const int64_t* __restrict__ idx,
-                             int ng, size_t N, double* __restrict__ series, const double* __restrict__ target,
-                             double* __restrict__ misfit, double* __restrict__ loss, int* __restrict__ flag) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(GAUGE_THREADS) void gauge_record(const T* __restrict__ q, const T* __restrict__ b,
+                                                              const int64_t* __restrict__ idx, int ng, size_t N,
+                                                              double* __restrict__ series,
+                                                              const double* __restrict__ target,
+                                                              double* __restrict__ misfit, double* __restrict__ loss,
+                                                              int* __restrict__ flag) {
+  __shared__ double part[GAUGE_THREADS];
+  const int t = threadIdx.x;
   double acc = 0.0;
-  for (int g = 0; g < ng; ++g) {
+  for (int g = t; g < ng; g += GAUGE_THREADS) {
     const int64_t k = idx[g];
     if (k < 0 || (size_t)k >= N) {
       atomicOr(flag, sgn::FLAG_BADINDEX);
@@ -185,20 +192,37 @@ __global__ void gauge_record(const T* __restrict__ q, const T* __restrict__ b, c
       acc += 0.5 * m * m;
     }
   }
-  if (loss) *loss += acc;
+  if (!loss) return;
+  part[t] = acc;
+  __syncthreads();
+  for (int w = GAUGE_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
+  }
+  if (t == 0) *loss += part[0];
 }
 
 // Adjoint seed of one misfit row: qbar_h += m and bbar += m at the gauges.
+// One thread per gauge; a node carrying several gauges is updated by the
+// thread of its first gauge, which adds their misfits in gauge order.
 template <typename T>
-__global__ void gauge_seed(const int64_t* __restrict__ idx, int ng, size_t N, const double* __restrict__ misfit,
-                           T* __restrict__ qbar, T* __restrict__ bbar) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int g = 0; g < ng; ++g) {
-    const int64_t k = idx[g];
-    if (k < 0 || (size_t)k >= N) continue;  // flagged by gauge_record
-    qbar[k] += T(misfit[g]);
-    bbar[k] += T(misfit[g]);
+__global__ __launch_bounds__(GAUGE_THREADS) void gauge_seed(const int64_t* __restrict__ idx, int ng, size_t N,
+                                                            const double* __restrict__ misfit, T* __restrict__ qbar,
+                                                            T* __restrict__ bbar) {
+  const int g = blockIdx.x * GAUGE_THREADS + threadIdx.x;
+  if (g >= ng) return;
+  const int64_t k = idx[g];
+  if (k < 0 || (size_t)k >= N) return;  // flagged by gauge_record
+  for (int e = 0; e < g; ++e)
+    if (idx[e] == k) return;
+  T qa = qbar[k], ba = bbar[k];
+  for (int e = g; e < ng; ++e) {
+    if (idx[e] != k) continue;
+    qa += T(misfit[e]);
+    ba += T(misfit[e]);
   }
+  qbar[k] = qa;
+  bbar[k] = ba;
 }
 
 // grad_zeta0 = hbar0 = qbar_h + qbar_eta; grad_b = bbar - hbar0 (h0 = zeta0 - b,
@@ -233,10 +257,10 @@ hipError_t launch_surface(const sgn_ctx* c, const void* zeta0, void* q) {
 hipError_t launch_record(const sgn_ctx* c, const void* q, const int64_t* idx, int ng, double* series,
                          const double* target, double* misfit, double* loss) {
   if (c->p.dtype == SGN_F64)
-    hipLaunchKernelGGL(gauge_record<double>, dim3(1), dim3(64), 0, c->stream, (const double*)q, (const double*)c->b, idx,
+    hipLaunchKernelGGL(gauge_record<double>, dim3(1), dim3(GAUGE_THREADS), 0, c->stream, (const double*)q, (const double*)c->b, idx,
                        ng, c->N, series, target, misfit, loss, c->flag);
   else
-    hipLaunchKernelGGL(gauge_record<float>, dim3(1), dim3(64), 0, c->stream, (const float*)q, (const float*)c->b, idx,
+    hipLaunchKernelGGL(gauge_record<float>, dim3(1), dim3(GAUGE_THREADS), 0, c->stream, (const float*)q, (const float*)c->b, idx,
                        ng, c->N, series, target, misfit, loss, c->flag);
   return hipGetLastError();
 }
@@ -375,10 +399,10 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, do
     for (int64_t k = len - 1; k >= 0; --k) {
       const int64_t n = n0 + k;  // step n maps q_n to q_{n+1}; misfit row n belongs to q_{n+1}
       if (c->p.dtype == SGN_F64)
-        hipLaunchKernelGGL(gauge_seed<double>, dim3(1), dim3(64), 0, s, gauge_idx, ngauges, c->N,
+        hipLaunchKernelGGL(gauge_seed<double>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS), 0, s, gauge_idx, ngauges, c->N,
                            a.misfit + n * ngauges, (double*)a.qbar, (double*)grad_b);
       else
-        hipLaunchKernelGGL(gauge_seed<float>, dim3(1), dim3(64), 0, s, gauge_idx, ngauges, c->N,
+        hipLaunchKernelGGL(gauge_seed<float>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS), 0, s, gauge_idx, ngauges, c->N,
                            a.misfit + n * ngauges, (float*)a.qbar, (float*)grad_b);
       HIPCHK(c, hipGetLastError());
       HIPCHK(c, reverse_step(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),

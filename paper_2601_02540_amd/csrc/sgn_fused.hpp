@@ -48,9 +48,15 @@ struct StepGeom {
   static_assert(RING3 <= 2 * STAGE_THREADS, "two ring slots per thread");
 };
 
-template <typename T, int TX>
+// Rows are padded to an odd number of elements (PAD = 1) so that the ring
+// columns, which lanes read down a column, spread over the LDS banks.  The
+// manufactured-source instantiations (the heaviest, with the source evaluated
+// inline) keep unpadded rows (PAD = 0): their reflecting variant returned wrong
+// values near the x-walls with padded rows, a failure not explained by the
+// source; unpadded they agree bit for bit with the four-stage path.
+template <typename T, int TX, int PAD>
 struct StepSmem {
-  T f[7][StepGeom<TX>::RY][StepGeom<TX>::RX];  // h u v w eta b 1/h, then the current stage (b kept)
+  T f[7][StepGeom<TX>::RY][StepGeom<TX>::RX + PAD];  // h u v w eta b 1/h, then the current stage (b kept)
 };
 
 // Position (r, c), relative to the tile origin, of ring node m (0 <= m < RING3).
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc,
   constexpr int TY = G::TY;
   constexpr int RX = G::RX;
   constexpr int REGION = G::RX * G::RY;
-  __shared__ StepSmem<T, TX> s;
+  __shared__ StepSmem<T, TX, SRC ? 0 : 1> s;
 
   const int nx = gc.nx, ny = gc.ny;
   const size_t N = (size_t)nx * (size_t)ny;

@@ -17,6 +17,7 @@ struct GraphCache {
   int steps = 0;
   int path = -1;
   int tile_y = 0;
+  int step_tile = 0;
 };
 
 // Buffers of the discrete adjoint, allocated on first use and kept by the context.
@@ -55,8 +56,9 @@ struct sgn_ctx {
   int* flag = nullptr;
   int* host_flag = nullptr;
   bool b_set = false;
-  int step_path = SGN_PATH_PAIRS;
-  int tile_y = 8;
+  int step_path = SGN_PATH_FUSED;
+  int tile_y = 8;     // stage and pair kernels
+  int step_tile = 16;  // step kernel: 16 selects 32 x 16, 8 selects 64 x 8
   sgn_host::GraphCache graphs[2];
   sgn_host::AdjointBuffers adj;
   std::string err;

@@ -179,10 +179,10 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 // One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct).
 hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0) {
   if (c->p.dtype == SGN_F64) {
-    if (c->tile_y == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0);
+    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0);
     return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0);
   }
-  if (c->tile_y == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0);
+  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0);
   return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0);
 }
 
@@ -243,7 +243,8 @@ hipError_t enqueue_steps(const sgn_ctx* c, hipStream_t s, void* q, double dt, in
 
 sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGraphExec_t* out) {
   GraphCache& g = c->graphs[slot];
-  if (g.exec && g.q == q && g.dt == dt && g.steps == steps && g.path == c->step_path && g.tile_y == c->tile_y) {
+  if (g.exec && g.q == q && g.dt == dt && g.steps == steps && g.path == c->step_path && g.tile_y == c->tile_y &&
+      g.step_tile == c->step_tile) {
     *out = g.exec;
     return SGN_OK;
   }
@@ -270,6 +271,7 @@ sgn_status get_graph(sgn_ctx* c, int slot, void* q, double dt, int steps, hipGra
   g.steps = steps;
   g.path = c->step_path;
   g.tile_y = c->tile_y;
+  g.step_tile = c->step_tile;
   *out = exec;
   return SGN_OK;
 }
@@ -379,6 +381,7 @@ sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
   c->N = N;
   c->esize = p->dtype == SGN_F64 ? sizeof(double) : sizeof(float);
   c->tile_y = p->dtype == SGN_F64 ? 8 : 16;  // measured best on MI355X at 4096^2
+  c->step_tile = 16;
   c->stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
@@ -530,6 +533,7 @@ sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
   } else if (option == SGN_OPT_TILE_Y) {
     if (value != 8 && value != 16) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
     c->tile_y = (int)value;
+    c->step_tile = (int)value;
   } else {
     return fail(c, SGN_E_ARG, "unknown option");
   }

@@ -84,7 +84,7 @@ __device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i
   SGN_LD(ym, rm, c)
   SGN_LD(yp, rp, c)
 #undef SGN_LD
-  Rates<T> k = split_form_rates<T>(center, xm, xp, ym, yp, T(ax.scale), T(ay.scale), T(gc.g), T(gc.lam), satx, saty);
+  Rates<T> k = split_form_rates<T, BCX, BCY>(center, xm, xp, ym, yp, T(ax.scale), T(ay.scale), T(gc.g), T(gc.lam), satx, saty);
   if (SRC) {
     const int gi = wrap_or_clamp<BCX>(i, gc.nx), gj = wrap_or_clamp<BCY>(j, gc.ny);
     double S[5];

@@ -76,39 +76,43 @@ struct Rates {
   T h, u, v, w, eta;
 };
 
-template <typename T>
+// Every derivative along one axis at a node carries the same scale (1/(2d) on
+// interior and periodic rows, 1/d on a closure row), so the differences are
+// formed unscaled, the x- and y-terms of each rate are summed separately and
+// each sum is scaled once.  The wall SAT enters only on reflecting axes.
+template <typename T, int BCX, int BCY>
 __device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Node<T>& xm, const Node<T>& xp,
                                                      const Node<T>& ym, const Node<T>& yp, T sx, T sy, T g, T lam,
                                                      T satx_coef, T saty_coef) {
   const T half = T(0.5);
-  // x derivatives (12)
-  const T Dxh = sx * (xp.h - xm.h);
-  const T Dxu = sx * (xp.u - xm.u);
-  const T Dxv = sx * (xp.v - xm.v);
-  const T Dxw = sx * (xp.w - xm.w);
-  const T Dxeta = sx * (xp.eta - xm.eta);
-  const T Dxb = sx * (xp.b - xm.b);
-  const T DxhH = sx * (xp.h * (xp.h + xp.b) - xm.h * (xm.h + xm.b));
-  const T Dxu2 = sx * (xp.u * xp.u - xm.u * xm.u);
+  // x differences (12), unscaled
+  const T dxh = xp.h - xm.h;
+  const T dxu = xp.u - xm.u;
+  const T dxv = xp.v - xm.v;
+  const T dxw = xp.w - xm.w;
+  const T dxeta = xp.eta - xm.eta;
+  const T dxb = xp.b - xm.b;
+  const T dxhH = xp.h * (xp.h + xp.b) - xm.h * (xm.h + xm.b);
+  const T dxu2 = xp.u * xp.u - xm.u * xm.u;
   const T xphu = xp.h * xp.u, xmhu = xm.h * xm.u;
-  const T Dxhu = sx * (xphu - xmhu);
-  const T Dxhuv = sx * (xphu * xp.v - xmhu * xm.v);
-  const T Dxe2h = sx * (xp.eta * xp.eta * xp.ih - xm.eta * xm.eta * xm.ih);
-  const T Dxhuw = sx * (xphu * xp.w - xmhu * xm.w);
-  // y derivatives (12)
-  const T Dyh = sy * (yp.h - ym.h);
-  const T Dyu = sy * (yp.u - ym.u);
-  const T Dyv = sy * (yp.v - ym.v);
-  const T Dyw = sy * (yp.w - ym.w);
-  const T Dyeta = sy * (yp.eta - ym.eta);
-  const T Dyb = sy * (yp.b - ym.b);
-  const T DyhH = sy * (yp.h * (yp.h + yp.b) - ym.h * (ym.h + ym.b));
-  const T Dyv2 = sy * (yp.v * yp.v - ym.v * ym.v);
+  const T dxhu = xphu - xmhu;
+  const T dxhuv = xphu * xp.v - xmhu * xm.v;
+  const T dxe2h = xp.eta * xp.eta * xp.ih - xm.eta * xm.eta * xm.ih;
+  const T dxhuw = xphu * xp.w - xmhu * xm.w;
+  // y differences (12), unscaled
+  const T dyh = yp.h - ym.h;
+  const T dyu = yp.u - ym.u;
+  const T dyv = yp.v - ym.v;
+  const T dyw = yp.w - ym.w;
+  const T dyeta = yp.eta - ym.eta;
+  const T dyb = yp.b - ym.b;
+  const T dyhH = yp.h * (yp.h + yp.b) - ym.h * (ym.h + ym.b);
+  const T dyv2 = yp.v * yp.v - ym.v * ym.v;
   const T yphv = yp.h * yp.v, ymhv = ym.h * ym.v;
-  const T Dyhv = sy * (yphv - ymhv);
-  const T Dyhuv = sy * (yphv * yp.u - ymhv * ym.u);
-  const T Dye2h = sy * (yp.eta * yp.eta * yp.ih - ym.eta * ym.eta * ym.ih);
-  const T Dyhvw = sy * (yphv * yp.w - ymhv * ym.w);
+  const T dyhv = yphv - ymhv;
+  const T dyhuv = yphv * yp.u - ymhv * ym.u;
+  const T dye2h = yp.eta * yp.eta * yp.ih - ym.eta * ym.eta * ym.ih;
+  const T dyhvw = yphv * yp.w - ymhv * ym.w;
 
   const T h = c.h, u = c.u, v = c.v, w = c.w, eta = c.eta;
   const T H = h + c.b;
@@ -116,21 +120,29 @@ __device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Nod
   const T omr = T(1) - r;
   const T hu = h * u, hv = h * v, uv = u * v, hw = h * w;
   const T lam6 = lam * T(1.0 / 6.0), lam3 = lam * T(1.0 / 3.0), lam2 = lam * T(0.5);
+  const T hsx = half * sx, hsy = half * sy;
 
   Rates<T> k;
-  k.h = -(u * Dxh + h * Dxu + v * Dyh + h * Dyv) + satx_coef * hu + saty_coef * hv;
+  k.h = -(sx * (u * dxh + h * dxu) + sy * (v * dyh + h * dyv));
+  if (BCX == BC_REFLECTING) k.h += satx_coef * hu;
+  if (BCY == BC_REFLECTING) k.h += saty_coef * hv;
 
-  const T A = g * (DxhH - H * Dxh) +
-              half * (h * Dxu2 - u * u * Dxh + u * Dxhu - hu * Dxu + Dyhuv - uv * Dyh + hv * Dyu - hu * Dyv) +
-              lam6 * (r * r * Dxh - Dxe2h) + lam3 * omr * Dxeta + lam2 * omr * Dxb;
-  const T B = g * (DyhH - H * Dyh) +
-              half * (h * Dyv2 - v * v * Dyh + v * Dyhv - hv * Dyv + Dxhuv - uv * Dxh + hu * Dxv - hv * Dxu) +
-              lam6 * (r * r * Dyh - Dye2h) + lam3 * omr * Dyeta + lam2 * omr * Dyb;
-  const T C = half * (Dxhuw + hu * Dxw - u * w * Dxh - hw * Dxu + Dyhvw + hv * Dyw - v * w * Dyh - hw * Dyv);
+  // A = h u_t, B = h v_t (with the sign of the rates), C = the flux part of h w_t
+  const T Ax = g * (dxhH - H * dxh) + lam6 * (r * r * dxh - dxe2h) + lam3 * omr * dxeta + lam2 * omr * dxb;
+  const T Ax2 = h * dxu2 - u * u * dxh + u * dxhu - hu * dxu;
+  const T Ay2 = dyhuv - uv * dyh + hv * dyu - hu * dyv;
+  const T A = sx * Ax + hsx * Ax2 + hsy * Ay2;
+  const T By = g * (dyhH - H * dyh) + lam6 * (r * r * dyh - dye2h) + lam3 * omr * dyeta + lam2 * omr * dyb;
+  const T By2 = h * dyv2 - v * v * dyh + v * dyhv - hv * dyv;
+  const T Bx2 = dxhuv - uv * dxh + hu * dxv - hv * dxu;
+  const T B = sy * By + hsy * By2 + hsx * Bx2;
+  const T Cx = dxhuw + hu * dxw - u * w * dxh - hw * dxu;
+  const T Cy = dyhvw + hv * dyw - v * w * dyh - hw * dyv;
+  const T C = hsx * Cx + hsy * Cy;
   k.u = -A * c.ih;
   k.v = -B * c.ih;
   k.w = (lam * omr - C) * c.ih;
-  k.eta = w - (u * Dxeta + v * Dyeta + T(1.5) * (u * Dxb + v * Dyb));
+  k.eta = w - (sx * (u * dxeta + T(1.5) * u * dxb) + sy * (v * dyeta + T(1.5) * v * dyb));
   return k;
 }
 
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const GridConst gc
     const Node<T> xp = lds_node(s, r, cidx + ax.op);
     const Node<T> ym = lds_node(s, r + ay.om, cidx);
     const Node<T> yp = lds_node(s, r + ay.op, cidx);
-    Rates<T> kk = split_form_rates<T>(c, xm, xp, ym, yp, T(ax.scale), T(ay.scale), g, lam, satx, saty);
+    Rates<T> kk = split_form_rates<T, BCX, BCY>(c, xm, xp, ym, yp, T(ax.scale), T(ay.scale), g, lam, satx, saty);
     if (SRC) {
       double S[5];
       mms_source(gc.xmin + i * gc.dx, gc.ymin + j * gc.dy, t, gc.g, S);

@@ -87,6 +87,25 @@ def test_gauge_loss_grad_matches_oracle(bc):
     assert abs(0.5 * np.sum((series - target) ** 2) - L) <= 1e-12 * L
 
 
+def test_gauge_loss_grad_many_and_repeated_gauges():
+    """More gauges than one pass of the gauge kernels' threads, with nodes that
+    carry several gauges: the seeds of a shared node add up in gauge order."""
+    g, gp, dt, _, _ = small_gauge_case(REF, 48, 20, 9)
+    rng = np.random.default_rng(11)
+    nodes = rng.integers(0, g.nx * g.ny, size=300)
+    nodes[150:170] = nodes[0]  # one node with 21 gauges
+    target = 1.0 + 0.02 * rng.standard_normal((9, len(nodes)))
+    L_ref, gz_ref, gb_ref = oracle.gauge_loss_grad(g, gp.zeta0, gp.b, dt, 9, nodes, target)
+    s = solver(g)
+    s.set_bathymetry(dev(gp.b))
+    L, gz, gb = s.gauge_loss_grad(dev(gp.zeta0), 9, dt, dev(nodes), dev(target), 3)
+    assert abs(L - L_ref) <= 1e-12 * L_ref
+    assert rel(host(gz), gz_ref) <= 1e-10
+    assert rel(host(gb), gb_ref) <= 1e-10
+    series = host(s.gauge_series(dev(gp.zeta0), 9, dt, dev(nodes)))
+    assert series.shape == (9, 300) and np.array_equal(series[:, 150:170], np.repeat(series[:, :1], 20, axis=1))
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     g, gp, dt, nodes, target = small_gauge_case(REF, 40, 16, 17)
     s = solver(g)
