@@ -143,7 +143,7 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
     return res
 
 
-def run_ensemble(count, steps, warmup, dtype, label):
+def run_ensemble(count, steps, warmup, dtype, label, path="fused"):
     """The ensemble workload: `count` instances of seeded sizes and boundaries in one batch."""
     import numpy as np
     import torch
@@ -154,6 +154,7 @@ def run_ensemble(count, steps, warmup, dtype, label):
     probs = W.ensemble(count, seed=4)
     log(f"[{label}] generated {count} instances in {time.perf_counter() - t0:.1f} s")
     batch = Batch([p.grid for p in probs], dtype)
+    batch.set_step_path(path)
     qs = [torch.from_numpy(p.q0).to(dtype).cuda().contiguous() for p in probs]
     for i, p in enumerate(probs):
         batch.set_bathymetry(i, torch.from_numpy(p.b).to(dtype).cuda().contiguous())
@@ -176,7 +177,7 @@ def run_ensemble(count, steps, warmup, dtype, label):
     m1, e1 = batch.mass_energy()
     nodes = batch.total_nodes()
     esize = 8 if dtype == torch.float64 else 4
-    values, launches = PATHS["pairs"]
+    values, launches = PATHS[path]
     achieved = values * esize * nodes * steps / sec / 1e9
     sizes = sorted({p.grid.nx for p in probs})
     res = {
@@ -189,6 +190,7 @@ def run_ensemble(count, steps, warmup, dtype, label):
         "ms_per_step": sec / steps * 1e3,
         "achieved_GBs": achieved,
         "frac": achieved / HBM_PEAK_GBS,
+        "path": path,
         "autotuned": {"tile_y": ty, "blocks_per_cu": bpc, "step_ms": tune_ms},
         "max_abs_energy_drift_rel": max(abs(b - a) / abs(a) for a, b in zip(e0, e1)),
         "max_abs_mass_drift_rel": max(abs(b - a) / abs(a) for a, b in zip(m0, m1)),
@@ -350,7 +352,8 @@ def main():
         variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T)
         variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T)
     if "ensemble" in chosen:
-        variants["ensemble_256_f32"] = run_ensemble(256, args.ensemble_steps, 4, torch.float32, "ensemble f32")
+        variants["ensemble_256_f32"] = run_ensemble(256, args.ensemble_steps, 4, torch.float32, "ensemble f32",
+                                                    "pairs" if P == "pairs" else "fused")
     if "small" in chosen:
         small = W.gaussian_bump_periodic(64, seed=1)
         variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T)

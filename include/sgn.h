@@ -182,8 +182,9 @@ sgn_status sgn_rhs_vjp(sgn_ctx* ctx, const void* q, const void* a, void* qbar, v
 
 /* Reverse of one RK4 step of size dt from q_n.  On entry qbar holds the
  * cotangent of q_{n+1}; on exit the cotangent of q_n.  bbar accumulates (+=)
- * the bathymetry cotangent.  The stage states are recomputed (four-stage
- * path) and reversed in the order k4, k3, k2, k1. */
+ * the bathymetry cotangent.  The stage states are recomputed (by the pair
+ * kernels on SGN_PATH_PAIRS, by the step kernel otherwise; the same values
+ * either way) and reversed in the order k4, k3, k2, k1. */
 sgn_status sgn_step_vjp(sgn_ctx* ctx, const void* q_n, double dt, void* qbar, void* bbar);
 
 /* Gauge series of a rollout: from the initial surface zeta0 (device plane),
@@ -201,8 +202,10 @@ sgn_status sgn_gauge_series(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, dou
  * both device planes.  The forward rollout stores a checkpoint every
  * checkpoint_every steps (0: ceil(sqrt(nsteps))); the reverse sweep
  * recomputes one segment at a time, keeping its states and stage states, and
- * runs the step VJPs backwards.  Memory: checkpoints plus 4*K+1 states for a
- * segment of K steps.  *loss is a host double.  Synchronizes. */
+ * runs the step VJPs backwards.  The forward steps follow the context's step
+ * path (pair kernels on SGN_PATH_PAIRS, the step kernel otherwise).  Memory:
+ * checkpoints plus 4*K+1 states for a segment of K steps.  *loss is a host
+ * double.  Synchronizes. */
 sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
                                int32_t ngauges, const double* target, int64_t checkpoint_every, double* loss,
                                void* grad_zeta0, void* grad_b);
@@ -212,11 +215,13 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, 
  *
  * Every instance has its own sgn_params (grid size, domain, boundary types, g,
  * lambda; all instances share one dtype; no source terms) and its own time
- * step.  The tiles of all instances form one work list; each RK4 step is two
- * launches of one persistent kernel over the whole list (the stage-pair
- * scheme of SGN_PATH_PAIRS, boundary variant chosen per instance), and steps
- * are replayed from a captured HIP graph.  Results are identical to advancing
- * each instance alone with sgn_step on the pair path with the same tile height.
+ * step.  The tiles of all instances form one work list; each RK4 step is one
+ * launch of a persistent kernel running the step tile of SGN_PATH_FUSED over
+ * the whole list (default), or two launches running the stage-pair tiles of
+ * SGN_PATH_PAIRS; the boundary variant is chosen per instance.  Steps are
+ * replayed from a captured HIP graph.  Results are identical, bit for bit, to
+ * advancing each instance alone with sgn_step (every step path forms the same
+ * values).
  *
  * The caller owns the states (n device pointers, each 5 planes of that
  * instance's ny*nx values in the batch dtype) and passes them with
@@ -240,9 +245,14 @@ sgn_status sgn_batch_step(sgn_batch* batch, const double* dt, int64_t nsteps);
 sgn_status sgn_batch_mass_energy(sgn_batch* batch, double* mass, double* energy);
 /* Per-instance CFL steps (rule of sgn_cfl_dt) into a host array of n doubles.  Synchronizes. */
 sgn_status sgn_batch_cfl_dt(sgn_batch* batch, double cfl, double* dt);
-/* Tile height (8 or 16) and persistent workgroups per compute unit (1..16). */
+/* SGN_PATH_FUSED (default) or SGN_PATH_PAIRS (SGN_E_UNSUPPORTED otherwise).
+ * Resets the tile height to the path's default (16; pairs in SGN_F64: 8). */
+sgn_status sgn_batch_set_step_path(sgn_batch* batch, int32_t path);
+/* Tile height (8 or 16; on the fused path 8 selects 64 x 8 tiles and 16
+ * selects 32 x 16) and persistent workgroups per compute unit (1..16). */
 sgn_status sgn_batch_set_tiling(sgn_batch* batch, int32_t tile_y, int32_t blocks_per_cu);
-/* Time every (tile height, workgroups per CU) candidate on one step from the
+/* Time every (tile height 8 or 16, 1..6 workgroups per CU) candidate of the
+ * current step path on one step from the
  * registered states into scratch (the states are read, never written), keep
  * the fastest and report it (any output may be NULL; ms = time of one step).
  * Synchronizes. */

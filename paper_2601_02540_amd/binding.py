@@ -91,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "sgn_batch_mass_energy": ([vp, dp, dp], st),
         "sgn_batch_cfl_dt": ([vp, d, dp], st),
         "sgn_batch_set_tiling": ([vp, ctypes.c_int32, ctypes.c_int32], st),
+        "sgn_batch_set_step_path": ([vp, ctypes.c_int32], st),
         "sgn_batch_autotune": ([vp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp], st),
         "sgn_batch_check": ([vp, ctypes.POINTER(ctypes.c_int32)], st),
         "sgn_batch_total_nodes": ([vp, ctypes.POINTER(ctypes.c_int64)], st),
@@ -377,6 +378,11 @@ class Batch:
         out = (ctypes.c_double * self.n)()
         self._chk(self.lib.sgn_batch_cfl_dt(self.h, float(cfl), out))
         return list(out)
+
+    def set_step_path(self, path: str):
+        """'fused' (one step kernel launch per RK4 step, default) or 'pairs'."""
+        self._chk(self.lib.sgn_batch_set_step_path(self.h, {"fused": SGN_PATH_FUSED, "pairs": SGN_PATH_PAIRS,
+                                                            "stages": SGN_PATH_STAGES}[path]))
 
     def set_tiling(self, tile_y: int, blocks_per_cu: int):
         self._chk(self.lib.sgn_batch_set_tiling(self.h, int(tile_y), int(blocks_per_cu)))

@@ -111,11 +111,14 @@ hipError_t launch_pair_save(const sgn_ctx* c, hipStream_t s, const void* Yin, co
   return launch_pair_save_t<float, PAIR, 8>(c, s, Yin, qn, acc, yb, ysave, qout, c1_acc, c1_y, c2_acc, c2_y);
 }
 
-// Forward RK4 step from `qn` into `qout` on the pair path, keeping the stage
-// states Y2, Y3, Y4 in `ys` (three consecutive state slots):
+// Forward RK4 step from `qn` into `qout`, keeping the stage states Y2, Y3, Y4
+// in `ys` (three consecutive state slots).  On the pair path:
 //   pair 1: k1 = f(qn), Y2 = qn + dt/2 k1 (saved), k2 = f(Y2), acc, Y3 = qn + dt/2 k2
 //   pair 2: k3 = f(Y3), Y4 = qn + dt k3 (saved), k4 = f(Y4), qout = acc + dt/3 k3 + dt/6 k4
+// (47 values of traffic per node); otherwise the step kernel writes the stage
+// states as it forms them (26 values).  Both give the same values bit for bit.
 hipError_t forward_step_keep(const sgn_ctx* c, hipStream_t s, const void* qn, void* ys, void* qout, double dt) {
+  if (c->step_path != SGN_PATH_PAIRS) return sgn_host::enqueue_step_into(c, s, qn, qout, dt, 0.0, ys);
   void* y2 = slot(ys, 0, c);
   void* y3 = slot(ys, 1, c);
   void* y4 = slot(ys, 2, c);
@@ -123,6 +126,13 @@ hipError_t forward_step_keep(const sgn_ctx* c, hipStream_t s, const void* qn, vo
                                      dt / 2.0);
   if (e) return e;
   return launch_pair_save<2>(c, s, y3, qn, c->acc, nullptr, y4, qout, dt / 3.0, dt, dt / 6.0, 0.0);
+}
+
+// One RK4 step of a rollout from `cur` into `oth`: the pair kernels on the pair
+// path, the step kernel otherwise.
+hipError_t rollout_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt) {
+  if (c->step_path == SGN_PATH_PAIRS) return sgn_host::enqueue_pair_step(c, s, cur, oth, dt, 0.0);
+  return sgn_host::enqueue_step_into(c, s, cur, oth, dt, 0.0, nullptr);
 }
 
 // Reverse of one RK4 step whose stage states are Y1 = qn and ys = (Y2, Y3, Y4).
@@ -330,7 +340,7 @@ sgn_status sgn_gauge_series(sgn_ctx* c, const void* zeta0, int64_t nsteps, doubl
   void* cur = a.state;
   void* oth = c->acc;
   for (int64_t n = 1; n <= nsteps; ++n) {
-    HIPCHK(c, sgn_host::enqueue_pair_step(c, c->stream, cur, oth, dt, 0.0));
+    HIPCHK(c, rollout_step(c, c->stream, cur, oth, dt));
     std::swap(cur, oth);
     HIPCHK(c, launch_record(c, cur, gauge_idx, ngauges, series + (n - 1) * ngauges, nullptr, nullptr, nullptr));
   }
@@ -373,14 +383,14 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, do
     return fail(c, SGN_E_ALLOC, "adjoint rollout storage");
   }
   hipStream_t s = c->stream;
-  // 1. forward rollout on the pair path: checkpoints every K steps, misfits, loss
+  // 1. forward rollout: checkpoints every K steps, misfits, loss
   HIPCHK(c, hipMemsetAsync(a.loss, 0, sizeof(double), s));
   HIPCHK(c, launch_surface(c, zeta0, a.state));
   void* cur = a.state;
   void* oth = c->acc;
   for (int64_t n = 0; n < nsteps; ++n) {
     if (n % K == 0) HIPCHK(c, hipMemcpyAsync(slot(a.ckpt, (size_t)(n / K), c), cur, sb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, sgn_host::enqueue_pair_step(c, s, cur, oth, dt, 0.0));
+    HIPCHK(c, rollout_step(c, s, cur, oth, dt));
     std::swap(cur, oth);
     HIPCHK(c, launch_record(c, cur, gauge_idx, ngauges, nullptr, target + n * ngauges, a.misfit + n * ngauges, a.loss));
   }

@@ -35,7 +35,7 @@ struct sgn_batch {
   sgn::InstDesc* h_desc = nullptr;  // pinned staging
   int* d_work = nullptr;
   int nwork = 0;
-  int work_ty = 0;
+  int work_key = 0;  // path and tile height the work list was built for
   int* d_flags = nullptr;
   int* h_flags = nullptr;
   double* d_partials = nullptr;
@@ -46,11 +46,12 @@ struct sgn_batch {
   std::vector<char> b_set;
   bool q_set = false;
   bool desc_dirty = true;
-  int tile_y = 8;
+  int path = SGN_PATH_FUSED;
+  int tile_y = 16;  // tile height; the step tile holds 512 nodes (8: 64 x 8, 16: 32 x 16), pair tiles are 64 wide
   int blocks_per_cu = 2;
   int num_cus = 256;
   hipGraphExec_t gexec = nullptr;
-  int g_ty = 0, g_bpc = 0;
+  int g_key = 0, g_bpc = 0;
   std::string err;
 };
 
@@ -81,13 +82,18 @@ void drop_graph(sgn_batch* b) {
   b->gexec = nullptr;
 }
 
-// (Re)build the work list and descriptors for the current tile height.
+int work_key(const sgn_batch* b) { return b->path * 100 + b->tile_y; }
+
+int tile_width(const sgn_batch* b) { return b->path == SGN_PATH_FUSED ? sgn::STEP_NODES / b->tile_y : sgn::TILE_X; }
+
+// (Re)build the work list and descriptors for the current path and tile height.
 sgn_status build_work(sgn_batch* b) {
-  if (b->work_ty == b->tile_y && b->d_work) return SGN_OK;
+  if (b->work_key == work_key(b) && b->d_work) return SGN_OK;
   std::vector<int> work;
+  const int tw = tile_width(b);
   for (int i = 0; i < b->n; ++i) {
     sgn::InstDesc& d = b->h_desc[i];
-    d.ntx = (b->params[i].nx + sgn::TILE_X - 1) / sgn::TILE_X;
+    d.ntx = (b->params[i].nx + tw - 1) / tw;
     d.nty = (b->params[i].ny + b->tile_y - 1) / b->tile_y;
     d.tile_base = (int)work.size();
     for (int t = 0; t < d.ntx * d.nty; ++t) work.push_back(i);
@@ -97,7 +103,7 @@ sgn_status build_work(sgn_batch* b) {
   BCHK(b, hipMalloc((void**)&b->d_work, work.size() * sizeof(int)));
   BCHK(b, hipMemcpy(b->d_work, work.data(), work.size() * sizeof(int), hipMemcpyHostToDevice));
   b->nwork = (int)work.size();
-  b->work_ty = b->tile_y;
+  b->work_key = work_key(b);
   b->desc_dirty = true;
   drop_graph(b);
   return SGN_OK;
@@ -116,12 +122,18 @@ sgn_status push_desc(sgn_batch* b) {
   return SGN_OK;
 }
 
-template <typename T, int TY>
-hipError_t launch_batch_pair_t(const sgn_batch* b, hipStream_t s, int pair, int parity, int bpc) {
+// Persistent grid: blocks_per_cu workgroups per CU, a multiple of 8 (one range
+// of the work list per XCD), no more than the work items.
+int persistent_grid(const sgn_batch* b, int bpc) {
   int grid = b->num_cus * bpc;
   grid = (grid + 7) / 8 * 8;
   const int maxgrid = (b->nwork + 7) / 8 * 8;
-  grid = std::max(8, std::min(grid, maxgrid));
+  return std::max(8, std::min(grid, maxgrid));
+}
+
+template <typename T, int TY>
+hipError_t launch_batch_pair_t(const sgn_batch* b, hipStream_t s, int pair, int parity, int bpc) {
+  const int grid = persistent_grid(b, bpc);
   if (pair == 1)
     hipLaunchKernelGGL((sgn::batch_pair_kernel<T, 1, TY>), dim3(grid), dim3(sgn::STAGE_THREADS), 0, s, b->d_desc,
                        b->d_work, b->nwork, parity, b->d_flags);
@@ -139,8 +151,22 @@ hipError_t launch_batch_pair(const sgn_batch* b, hipStream_t s, int pair, int pa
                          : launch_batch_pair_t<float, 8>(b, s, pair, parity, b->blocks_per_cu);
 }
 
+template <typename T, int TX>
+hipError_t launch_batch_step_t(const sgn_batch* b, hipStream_t s, int parity, int bpc) {
+  hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX>), dim3(persistent_grid(b, bpc)), dim3(sgn::STAGE_THREADS), 0, s,
+                     b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+  return hipGetLastError();
+}
+
 // One RK4 step of every instance from the buffer selected by parity into the other.
 hipError_t enqueue_batch_step(const sgn_batch* b, hipStream_t s, int parity) {
+  if (b->path == SGN_PATH_FUSED) {
+    if (b->dtype == SGN_F64)
+      return b->tile_y == 16 ? launch_batch_step_t<double, 32>(b, s, parity, b->blocks_per_cu)
+                             : launch_batch_step_t<double, 64>(b, s, parity, b->blocks_per_cu);
+    return b->tile_y == 16 ? launch_batch_step_t<float, 32>(b, s, parity, b->blocks_per_cu)
+                           : launch_batch_step_t<float, 64>(b, s, parity, b->blocks_per_cu);
+  }
   hipError_t e = launch_batch_pair(b, s, 1, parity);
   if (e) return e;
   return launch_batch_pair(b, s, 2, parity);
@@ -190,7 +216,7 @@ sgn_status sgn_batch_create(int32_t n, const sgn_params* params, void* stream, s
   b->n = n;
   b->dtype = dtype;
   b->esize = dtype == SGN_F64 ? sizeof(double) : sizeof(float);
-  b->tile_y = dtype == SGN_F64 ? 8 : 16;
+  b->tile_y = 16;
   b->stream = (hipStream_t)stream;
   for (int i = 0; i < n; ++i) {
     const sgn_params& p = params[i];
@@ -352,7 +378,7 @@ sgn_status sgn_batch_step(sgn_batch* b, const double* dt, int64_t nsteps) {
   int64_t left = nsteps;
   const int64_t per_graph = 2 * BATCH_GRAPH_DOUBLE_STEPS;
   if (left >= per_graph) {
-    if (!b->gexec || b->g_ty != b->tile_y || b->g_bpc != b->blocks_per_cu) {
+    if (!b->gexec || b->g_key != work_key(b) || b->g_bpc != b->blocks_per_cu) {
       drop_graph(b);
       BCHK(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
       hipError_t le = hipSuccess;
@@ -373,7 +399,7 @@ sgn_status sgn_batch_step(sgn_batch* b, const double* dt, int64_t nsteps) {
         b->gexec = nullptr;
         return bhip(b, ie, "hipGraphInstantiate");
       }
-      b->g_ty = b->tile_y;
+      b->g_key = work_key(b);
       b->g_bpc = b->blocks_per_cu;
     }
     for (; left >= per_graph; left -= per_graph) BCHK(b, hipGraphLaunch(b->gexec, b->stream));
@@ -446,6 +472,16 @@ sgn_status sgn_batch_cfl_dt(sgn_batch* b, double cfl, double* dt) {
   return SGN_OK;
 }
 
+sgn_status sgn_batch_set_step_path(sgn_batch* b, int32_t path) {
+  if (!b) return SGN_E_ARG;
+  if (path != SGN_PATH_FUSED && path != SGN_PATH_PAIRS)
+    return bfail(b, SGN_E_UNSUPPORTED, "a batch steps on the fused or the pair path");
+  b->path = path;
+  b->tile_y = (path == SGN_PATH_PAIRS && b->dtype == SGN_F64) ? 8 : 16;  // measured best on MI355X
+  drop_graph(b);
+  return build_work(b);
+}
+
 sgn_status sgn_batch_set_tiling(sgn_batch* b, int32_t tile_y, int32_t blocks_per_cu) {
   if (!b) return SGN_E_ARG;
   if (tile_y != 8 && tile_y != 16) return bfail(b, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
@@ -470,7 +506,7 @@ sgn_status sgn_batch_autotune(sgn_batch* b, const double* dt, int32_t* tile_y, i
   // Candidates are timed on one step from q into the scratch buffer (parity 0),
   // which reads the states but never writes them.
   const int tys[2] = {8, 16};
-  const int bpcs[4] = {1, 2, 3, 4};
+  const int bpcs[6] = {1, 2, 3, 4, 5, 6};
   double best = 1e300;
   int best_ty = b->tile_y, best_bpc = b->blocks_per_cu;
   hipEvent_t e0, e1;

@@ -8,8 +8,12 @@
 // of the same instance (and their shared halo rows) stay in one L2.  Each work
 // item runs the same pair_tile code as the single-problem kernel, with the
 // boundary variant chosen per instance at run time (uniform per workgroup).
+//
+// With the step kernel (the default), one launch per RK4 step runs the fused
+// step tile on every work item instead.
 #pragma once
 
+#include "sgn_fused.hpp"
 #include "sgn_pair.hpp"
 
 namespace sgn {
@@ -66,6 +70,40 @@ __global__ __launch_bounds__(STAGE_THREADS) void batch_pair_kernel(const InstDes
       case 1: batch_tile<T, PAIR, TY, 0, 1>(s, d, i0, j0, parity, flags + inst); break;
       case 2: batch_tile<T, PAIR, TY, 1, 0>(s, d, i0, j0, parity, flags + inst); break;
       default: batch_tile<T, PAIR, TY, 1, 1>(s, d, i0, j0, parity, flags + inst); break;
+    }
+    __syncthreads();
+  }
+}
+
+// One RK4 step of every instance by the step tile (tiles of TX x 512/TX).
+// parity 0: state in q, written to acc; parity 1: state in acc, written to q.
+template <typename T, int TX>
+__global__ __launch_bounds__(STAGE_THREADS) void batch_step_kernel(const InstDesc* __restrict__ desc,
+                                                                   const int* __restrict__ work_inst, int nwork,
+                                                                   int parity, int* __restrict__ flags) {
+  constexpr int TY = StepGeom<TX>::TY;
+  __shared__ StepSmem<T, TX, 1> s;
+  const int xcd = blockIdx.x & 7;
+  const int k = blockIdx.x >> 3;
+  const int blocks_per_xcd = gridDim.x >> 3;  // the grid is a multiple of 8
+  const int start = (int)((long long)nwork * xcd / 8);
+  const int end = (int)((long long)nwork * (xcd + 1) / 8);
+  for (int w = start + k; w < end; w += blocks_per_xcd) {
+    const int inst = work_inst[w];
+    const InstDesc d = desc[inst];
+    const int t = w - d.tile_base;
+    const int i0 = (t % d.ntx) * TX;
+    const int j0 = (t / d.ntx) * TY;
+    const T* cur = (const T*)(parity ? d.acc : d.q);
+    T* oth = (T*)(parity ? d.q : d.acc);
+    const T* b = (const T*)d.b;
+    const double dt = d.dt;
+    const T c6 = T(dt / 6.0), c3 = T(dt / 3.0), c2 = T(dt / 2.0), c1 = T(dt);
+    switch (d.gc.bc_x * 2 + d.gc.bc_y) {
+      case 0: step_tile<T, 0, 0, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+      case 1: step_tile<T, 0, 1, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+      case 2: step_tile<T, 1, 0, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+      default: step_tile<T, 1, 1, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
     }
     __syncthreads();
   }

@@ -90,24 +90,21 @@ __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
   }
 }
 
-template <typename T, int BCX, int BCY, bool SRC, int TX>
-__global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
-                                                             const T* __restrict__ bplane, T* __restrict__ qout,
-                                                             T c6, T c3, T c2, T c1, double t0, double dt,
-                                                             int* __restrict__ flag) {
+// One tile (origin i0, j0) of one RK4 step, executed by a whole workgroup.
+// SAVE (the adjoint's recomputation): also write the intermediate stages
+// Y2, Y3, Y4 of the owned nodes to ysave, three consecutive states.
+// The caller synchronizes the workgroup before reusing `s` for another tile.
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD>
+__device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridConst& gc, int i0, int j0,
+                                          const T* __restrict__ q, const T* __restrict__ bplane,
+                                          T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
+                                          int* __restrict__ flag, T* __restrict__ ysave) {
   using G = StepGeom<TX>;
-  constexpr int TY = G::TY;
   constexpr int RX = G::RX;
   constexpr int REGION = G::RX * G::RY;
-  __shared__ StepSmem<T, TX, SRC ? 0 : 1> s;
 
   const int nx = gc.nx, ny = gc.ny;
   const size_t N = (size_t)nx * (size_t)ny;
-  const int ntx = (nx + TX - 1) / TX;
-  const int nty = (ny + TY - 1) / TY;
-  const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  const int i0 = (tile % ntx) * TX;
-  const int j0 = (tile / ntx) * TY;
   const int tid = threadIdx.x;
 
   // 1. Stage q and b with the four-node halo (periodic wrap or wall clamp).
@@ -202,7 +199,13 @@ __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc,
           acc[k][f] = acc[k][f] + ca * kv[f];
           ro[k][f] = qo[k][f] + cy * kv[f];
         }
-      } else {
+      }
+      if (SAVE && st < 4 && i < nx && j < ny) {
+        T* ys = ysave + (size_t)(st - 1) * 5 * N + (size_t)j * nx + i;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) ys[f * N] = ro[k][f];
+      }
+      if (st == 4) {
         const size_t o = (size_t)j * nx + i;
         T nv[5];
 #pragma unroll
@@ -258,6 +261,20 @@ __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc,
     __syncthreads();
   }
   if (health) atomicOr(flag, health);
+}
+
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false>
+__global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
+                                                             const T* __restrict__ bplane, T* __restrict__ qout,
+                                                             T c6, T c3, T c2, T c1, double t0, double dt,
+                                                             int* __restrict__ flag, T* __restrict__ ysave) {
+  constexpr int TY = StepGeom<TX>::TY;
+  __shared__ StepSmem<T, TX, SRC ? 0 : 1> s;
+  const int ntx = (gc.nx + TX - 1) / TX;
+  const int nty = (gc.ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  step_tile<T, BCX, BCY, SRC, TX, SAVE>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane, qout, c6, c3, c2,
+                                        c1, t0, dt, flag, ysave);
 }
 
 }  // namespace sgn

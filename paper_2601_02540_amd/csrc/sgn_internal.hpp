@@ -76,6 +76,11 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
                              void* out, double c_acc, double c_y, double t);
 // one RK4 step on the pair path from `cur` into `oth`
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t);
+// One RK4 step by the step kernel from `cur` into `oth` (distinct buffers);
+// with `ysave` non-null the stage states Y2, Y3, Y4 go to three consecutive
+// state slots there (no source terms).
+hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
+                             void* ysave);
 
 }  // namespace sgn_host
 

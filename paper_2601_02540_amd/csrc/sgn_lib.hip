@@ -148,7 +148,8 @@ hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const v
 }
 
 template <typename T, int TX>
-hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0) {
+hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
+                           void* ysave) {
   constexpr int TY = sgn::STEP_NODES / TX;
   const int ntx = (c->p.nx + TX - 1) / TX;
   const int nty = (c->p.ny + TY - 1) / TY;
@@ -157,11 +158,18 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
   const T* qp = (const T*)qin;
   const T* bp = (const T*)c->b;
   T* op = (T*)qout;
-#define SGN_LAUNCH(BX, BY, S)                                                                                  \
-  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX>), grid, block, 0, s, c->gc, qp, bp, op, (T)(dt / 6.0), \
-                     (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag)
+  T* ys = (T*)ysave;
+#define SGN_LAUNCH_K(BX, BY, S, SV)                                                                             \
+  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV>), grid, block, 0, s, c->gc, qp, bp, op,           \
+                     (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys)
+#define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false)
   const int bx = c->p.bc_x, by = c->p.bc_y;
-  if (!src) {
+  if (ys) {  // stage saving (no source terms)
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true);
+    else SGN_LAUNCH_K(1, 1, false, true);
+  } else if (!src) {
     if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
     else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
     else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, false);
@@ -173,17 +181,20 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
     else SGN_LAUNCH(1, 1, true);
   }
 #undef SGN_LAUNCH
+#undef SGN_LAUNCH_K
   return hipGetLastError();
 }
 
-// One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct).
-hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0) {
+// One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct);
+// with `ysave`, also the stage states Y2, Y3, Y4 (three consecutive states).
+hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
+                        void* ysave = nullptr) {
   if (c->p.dtype == SGN_F64) {
-    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0);
-    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0);
+    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave);
+    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave);
   }
-  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0);
-  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0);
+  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave);
+  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave);
 }
 
 // Two RK4 steps on the fused path: q -> acc -> q.
@@ -311,6 +322,11 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
     case sgn::MODE_MID: return launch_stage<sgn::MODE_MID>(c, s, Y, qn, acc, out, c_acc, c_y, t);
     default: return launch_stage<sgn::MODE_LAST>(c, s, Y, qn, acc, out, c_acc, c_y, t);
   }
+}
+
+hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
+                             void* ysave) {
+  return ::launch_fused(c, s, cur, oth, dt, t, ysave);
 }
 
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {

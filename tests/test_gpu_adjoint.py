@@ -106,6 +106,25 @@ def test_gauge_loss_grad_many_and_repeated_gauges():
     assert series.shape == (9, 300) and np.array_equal(series[:, 150:170], np.repeat(series[:, :1], 20, axis=1))
 
 
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_gradient_same_on_pair_and_fused_paths(bc):
+    """The rollout and the segment recomputation run on the context's step path;
+    the pair kernels and the step kernel form the same states bit for bit, so
+    the loss and both gradients agree exactly."""
+    g, gp, dt, nodes, target = small_gauge_case(bc, 70, 36, 13)
+    outs = []
+    for path in ("pairs", "fused"):
+        s = solver(g)
+        s.set_step_path(path)
+        s.set_bathymetry(dev(gp.b))
+        L, gz, gb = s.gauge_loss_grad(dev(gp.zeta0), 13, dt, dev(nodes), dev(target), 4)
+        series = host(s.gauge_series(dev(gp.zeta0), 13, dt, dev(nodes)))
+        outs.append((L, host(gz), host(gb), series))
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1:], outs[1][1:]):
+        assert np.array_equal(a, b)
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     g, gp, dt, nodes, target = small_gauge_case(REF, 40, 16, 17)
     s = solver(g)

@@ -1,9 +1,9 @@
 """GPU tests of the ensemble path (sgn_batch_*): uneven grids, mixed boundaries,
-one persistent launch per stage pair.
+one persistent launch per RK4 step (step tiles) or per stage pair (pair tiles).
 
 Each instance must equal, bit for bit, the same problem advanced alone on the
-pair path with the same tile height (same per-tile code), and match the FP64
-oracle within 1e-12 field-relative."""
+same step path with the same tile shape (same per-tile code), and match the
+FP64 oracle within 1e-12 field-relative."""
 
 import math
 
@@ -35,8 +35,10 @@ def small_ensemble(seed=7, count=10):
     return probs
 
 
-def run_batch(probs, dtype, dts, nsteps, tiling=None):
+def run_batch(probs, dtype, dts, nsteps, tiling=None, path=None):
     batch = Batch([p[0] for p in probs], dtype)
+    if path:
+        batch.set_step_path(path)
     if tiling:
         batch.set_tiling(*tiling)
     qs = [dev(p[1], dtype) for p in probs]
@@ -48,15 +50,16 @@ def run_batch(probs, dtype, dts, nsteps, tiling=None):
     return batch, [host(q) for q in qs]
 
 
+@pytest.mark.parametrize("path", ["fused", "pairs"])
 @pytest.mark.parametrize("dtype,ty", [(torch.float64, 8), (torch.float64, 16), (torch.float32, 16)])
 @pytest.mark.parametrize("nsteps", [1, 2, 11])
-def test_batch_equals_single_pair_path(dtype, ty, nsteps):
+def test_batch_equals_single_solver(path, dtype, ty, nsteps):
     probs = small_ensemble()
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
-    _, outs = run_batch(probs, dtype, dts, nsteps, (ty, 2))
+    _, outs = run_batch(probs, dtype, dts, nsteps, (ty, 2), path)
     for (g, q, b), dt, got in zip(probs, dts, outs):
         s = Solver(g, dtype)
-        s.set_step_path("pairs")
+        s.set_step_path(path)
         s.set_tile_y(ty)
         s.set_bathymetry(dev(b, dtype))
         qd = dev(q, dtype)
@@ -64,14 +67,25 @@ def test_batch_equals_single_pair_path(dtype, ty, nsteps):
         assert np.array_equal(got, host(qd)), (g, nsteps)
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("path", ["fused", "pairs"])
+def test_batch_matches_oracle(path):
     probs = small_ensemble(seed=8, count=6)
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
-    _, outs = run_batch(probs, torch.float64, dts, 3)
+    _, outs = run_batch(probs, torch.float64, dts, 3, path=path)
     for (g, q, b), dt, got in zip(probs, dts, outs):
         ref = oracle.rk4(g, q, b, dt, 3)
         err = field_rel_err(got, ref, STATE_FLOORS)
         assert np.all(err <= F64_TOL), (g, err)
+
+
+def test_batch_paths_agree_bitwise():
+    """The step tiles and the pair tiles form the same values."""
+    probs = small_ensemble(seed=12, count=7)
+    dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
+    _, a = run_batch(probs, torch.float64, dts, 5, path="fused")
+    _, b = run_batch(probs, torch.float64, dts, 5, path="pairs")
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
 
 
 def test_batch_autotune_reads_states_only():
@@ -83,7 +97,7 @@ def test_batch_autotune_reads_states_only():
     batch.set_states(qs)
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
     ty, bpc, ms = batch.autotune(dts)
-    assert ty in (8, 16) and 1 <= bpc <= 4 and ms > 0
+    assert ty in (8, 16) and 1 <= bpc <= 6 and ms > 0
     for q, p in zip(qs, probs):
         assert np.array_equal(host(q), p[1])
     batch.step(dts, 2)
@@ -137,3 +151,5 @@ def test_batch_rejects_bad_input():
     batch = Batch([g, g])
     with pytest.raises(SgnError):  # bathymetry not set
         batch.step([1e-3, 1e-3], 1)
+    with pytest.raises(SgnError):  # no batch kernel for the four-stage path
+        batch.set_step_path("stages")
