@@ -51,6 +51,15 @@ PATHS = {"pairs": (37, 2), "stages": (84, 4), "fused": (11, 1)}
 # reciprocal counts 1, a fused multiply-add 2.
 FLOPS_PER_NODE_STEP = 4 * 178 + 70
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# HBM traffic of the step kernel on the default workload (4096^2 periodic FP64,
+# 32 x 16 tiles), from the FETCH_SIZE and WRITE_SIZE passes summarized in
+# profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
+# 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
+# node and launch.  Reported only while the kernel sources hash to the value
+# they had when the counters were taken.
+STEP_TRAFFIC_BYTES_PER_NODE = (1184900381.5 + 671088640.0) / 16777216
+STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_fused.hpp")
+STEP_SOURCES_SHA256 = "6b955712b60c964b456bab1ea915af44e06846851033263ad4ff92b12083c356"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
@@ -268,6 +277,15 @@ def cpu_baseline(problem, steps=1):
                       f"({sec:.1f} s, single-threaded C++ -O2 -ffp-contract=off)"}
 
 
+def step_sources_unchanged():
+    import hashlib
+    h = hashlib.sha256()
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_02540_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest() == STEP_SOURCES_SHA256
+
+
 def roofline(path, res, cells):
     """Roofline entry of the main run's dominant kernel.  The step kernel moves
     only the method's own 11 values per node and step; its arithmetic intensity
@@ -276,7 +294,10 @@ def roofline(path, res, cells):
     vector peak, with its HBM figures beside it.  The pair and stage kernels
     are reported against HBM."""
     values, launches = PATHS[path]
-    common = {"kernel": KERNELS[path], "traffic": None,
+    traffic = None
+    if path == "fused" and cells == 4096 * 4096 and res["tile_y"] in (None, 16) and step_sources_unchanged():
+        traffic = STEP_TRAFFIC_BYTES_PER_NODE * cells
+    common = {"kernel": KERNELS[path], "traffic": traffic, "traffic_unit": "bytes per launch",
               "algorithmic_bytes_per_launch_per_node": values / launches * 8,
               "algorithmic_bytes_per_step_per_node": values * 8}
     if path == "fused":
