@@ -63,7 +63,7 @@ STEP_SOURCES_SHA256 = "6b955712b60c964b456bab1ea915af44e06846851033263ad4ff92b12
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
-ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths"}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper"}
 
 
 def log(msg):
@@ -261,6 +261,40 @@ def run_adjoint(n, steps, label):
     return res
 
 
+def run_paper_setups(path, tile_y):
+    """The paper's scaling study (solitary wave over a Gaussian obstacle, nx = 2^n,
+    ny = nx/2, run to t = 12 in the paper) and its long-term cylindrical dam break
+    (10^8 nodes, run to t = 300).  Fixed-step RK4 at CFL 0.5 here, so the
+    projected runtimes (timed steps x steps to the final time) are context for
+    the paper's adaptive runs, not a like-for-like comparison."""
+    import math
+    from paper_2601_02540_amd import workloads as W
+    out = {}
+    for nx in (1024, 2048, 4096, 8192):
+        p = W.gaussian_obstacle(nx)
+        r = run_gpu(p, torch_f64(), 100, 8, f"gaussian obstacle {nx}x{nx // 2}", path, tile_y)
+        steps_to_end = math.ceil(12.0 / r["dt"])
+        out[f"gaussian_obstacle_{nx}x{nx // 2}"] = {
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "ms_per_rhs": r["ms_per_step"] / 4,
+            "dt": r["dt"], "steps_to_t12": steps_to_end,
+            "projected_runtime_to_t12_s": steps_to_end * r["ms_per_step"] / 1e3,
+            "energy_drift_rel": r["energy_drift_rel"], "mass_drift_rel": r["mass_drift_rel"]}
+    p = W.cylindrical_dam_break(10000, 1100.0)
+    r = run_gpu(p, torch_f64(), 100, 8, "cylindrical dam break 10000x10000", path, tile_y)
+    steps_to_end = math.ceil(300.0 / r["dt"])
+    out["cylindrical_dam_break_10000x10000"] = {
+        "value": r["value"], "ms_per_step": r["ms_per_step"], "dt": r["dt"], "steps_to_t300": steps_to_end,
+        "projected_runtime_to_t300_s": steps_to_end * r["ms_per_step"] / 1e3,
+        "energy_drift_rel": r["energy_drift_rel"], "mass_drift_rel": r["mass_drift_rel"]}
+    log(f"[paper setups] dam break projected to t=300: {out['cylindrical_dam_break_10000x10000']['projected_runtime_to_t300_s']:.0f} s")
+    return out
+
+
+def torch_f64():
+    import torch
+    return torch.float64
+
+
 def cpu_baseline(problem, steps=1):
     """The FP64 oracle (single thread, as written) on the same workload."""
     import numpy as np
@@ -331,7 +365,7 @@ def main():
     ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
-                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths (default all)")
+                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper (default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
@@ -382,6 +416,8 @@ def main():
         variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
+    if "paper" in chosen:
+        variants["paper_setups"] = run_paper_setups(P, T)
     if "paths" in chosen:
         for other in sorted(PATHS):
             if other != P:

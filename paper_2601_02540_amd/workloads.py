@@ -215,6 +215,41 @@ def ensemble(count: int = 256, seed: int = 4, sizes=(128, 256, 512, 1024), lam: 
     return out
 
 
+
+# ---------------------------------------------------------------------------
+# Two of the paper's own setups (their initial conditions are given in full).
+
+def gaussian_obstacle(nx: int = 1600, ny: Optional[int] = None, lam: float = 500.0) -> Problem:
+    """Solitary wave over a Gaussian obstacle (Section "Solitary Wave over a Gaussian
+    Obstacle"): periodic [-5,35] x [-10,10], bathymetry b = 0.1 exp(-(x^2+y^2)/2), still
+    depth 0.2, a solitary wave of amplitude 0.0365 with its crest at x = -3 moving in +x
+    (surface from the classical closed form, h = zeta - b, u from the closed form, v = 0).
+    The paper's spacing 0.025 is nx = 1600, ny = 800; its scaling study uses nx = 2^n,
+    ny = nx/2 (square cells)."""
+    ny = nx // 2 if ny is None else ny
+    grid = Grid(nx, ny, -5.0, 35.0, -10.0, 10.0, PERIODIC, PERIODIC, 9.81, lam)
+    X, Y = _mesh(grid)
+    b = 0.1 * np.exp(-(X * X + Y * Y) / 2.0)
+    zeta, u = classical_soliton(X, 0.0, 0.0365, 0.2, grid.g, -3.0)
+    q = _empty_state(grid)
+    q[0] = zeta - b
+    q[1] = u
+    return Problem(grid, q, b, f"gaussian_obstacle_{nx}x{ny}", 0)
+
+
+def cylindrical_dam_break(n: int = 10000, half_width: float = 1100.0, lam: float = 500.0) -> Problem:
+    """Smoothed cylindrical dam break (Section "Dam Break Problems"; the long-term run
+    uses [-1100,1100]^2 at spacing 0.22, i.e. 10000^2 nodes): reflecting walls, flat
+    bottom, h = 1 + 0.4 (1 - tanh((r - 20)/6.5)), zero velocity."""
+    grid = Grid(n, n, -half_width, half_width, -half_width, half_width, REFLECTING, REFLECTING, 9.81, lam)
+    x, y = grid.x_nodes(), grid.y_nodes()
+    q = np.zeros((5, n, n))
+    for j0 in range(0, n, 1024):  # row blocks keep the temporaries small at 10^8 nodes
+        yy = y[j0:j0 + 1024, None]
+        r = np.sqrt(x[None, :] ** 2 + yy ** 2)
+        q[0, j0:j0 + 1024] = 1.0 + 0.4 * (1.0 - np.tanh((r - 20.0) / 6.5))
+    return Problem(grid, q, np.zeros((n, n)), f"cylindrical_dam_break_{n}", 0)
+
 @dataclasses.dataclass
 class GaugeProblem:
     """Initial surface zeta0 and bathymetry b (the two parameters), gauge node indices,

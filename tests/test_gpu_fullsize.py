@@ -18,56 +18,17 @@ import torch
 
 import oracle
 from paper_2601_02540_amd import workloads as W
-from gpu_util import STATE_FLOORS, dev, field_rel_err, host, solver
+from gpu_util import STATE_FLOORS, check_windows as _check, dev, field_rel_err, host, solver
 
 pytestmark = pytest.mark.gpu
 
 PER, REF = W.PERIODIC, W.REFLECTING
 STEPS = 8        # one graph replay of the benchmark's step loop
-R = 4 * STEPS    # reach of STEPS steps
 WIN = 32         # compared nodes per window and axis
 
 
-def axis_window(kind, n, bc, start=0):
-    """Indices of a window along one axis, the window grid's boundary type and
-    the slice of compared nodes."""
-    if kind == "wall_lo":
-        assert bc == REF
-        return np.arange(0, WIN + R), REF, slice(0, WIN)
-    if kind == "wall_hi":
-        assert bc == REF
-        return np.arange(n - WIN - R, n), REF, slice(R, R + WIN)
-    idx = np.arange(start - R, start + WIN + R)
-    if bc == PER:
-        idx = idx % n
-    else:
-        assert idx[0] >= 0 and idx[-1] < n
-    return idx, PER, slice(R, R + WIN)
-
-
-def window_grid(grid, ny, nx, bcy, bcx):
-    dx, dy = grid.spacing()
-    lx = nx * dx if bcx == PER else (nx - 1) * dx
-    ly = ny * dy if bcy == PER else (ny - 1) * dy
-    return W.Grid(nx, ny, 0.0, lx, 0.0, ly, bcx, bcy, grid.g, grid.lam)
-
-
 def check_windows(grid, q0, b, got, dt, windows, f32=False):
-    for (ky, sy), (kx, sx) in windows:
-        ry, bcy, keep_y = axis_window(ky, grid.ny, grid.bc_y, sy)
-        rx, bcx, keep_x = axis_window(kx, grid.nx, grid.bc_x, sx)
-        wg = window_grid(grid, len(ry), len(rx), bcy, bcx)
-        qw = q0[:, ry][:, :, rx]
-        bw = b[ry][:, rx]
-        ref = oracle.rk4(wg, qw, bw, dt, STEPS)[:, keep_y, keep_x]
-        g = got[:, ry][:, :, rx][:, keep_y, keep_x]
-        err = field_rel_err(g, ref, STATE_FLOORS)
-        if f32:
-            o32 = oracle.rk4_f32(wg, qw, bw, dt, STEPS).astype(np.float64)[:, keep_y, keep_x]
-            bound = field_rel_err(o32, ref, STATE_FLOORS)
-            assert np.all(err <= 4 * bound + 1e-6), ((ky, sy), (kx, sx), err, bound)
-        else:
-            assert np.all(err <= 1e-12), ((ky, sy), (kx, sx), err)
+    _check(grid, q0, b, got, dt, STEPS, windows, WIN, f32)
 
 
 def full_run(bc, dtype):
