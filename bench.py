@@ -290,6 +290,56 @@ def run_paper_setups(path, tile_y):
     return out
 
 
+def run_long_dam_break(path, tile_y, t_end=300.0):
+    """The paper's long-term cylindrical dam break run to the end: 10^8 nodes,
+    FP64, [-1100,1100]^2, reflecting, fixed-step RK4 at CFL 0.5 to t = 300.
+    Logs progress every 5000 steps."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2601_02540_amd import workloads as W
+    from paper_2601_02540_amd.binding import Solver
+    p = W.cylindrical_dam_break(10000, 1100.0)
+    g = p.grid
+    s = Solver(g, torch.float64)
+    s.set_step_path(path)
+    if tile_y is not None:
+        s.set_tile_y(tile_y)
+    b = torch.from_numpy(p.b).cuda()
+    q = torch.from_numpy(p.q0).cuda()
+    s.set_bathymetry(b)
+    s.init_aux(q)
+    dt0 = s.cfl_dt(q, 0.5)
+    nsteps = math.ceil(t_end / dt0)
+    dt = t_end / nsteps
+    m0, e0 = s.mass_energy(q)
+    log(f"[long dam break] {nsteps} steps of {dt:.6e} to t = {t_end}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < nsteps:
+        k = min(5000, nsteps - done)
+        s.step(q, dt, k, t0=done * dt)
+        s.check()
+        done += k
+        log(f"[long dam break] {done}/{nsteps} steps, {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m1, e1 = s.mass_energy(q)
+    e_rest = lake_at_rest_energy(g, p.b, m0)
+    eta = q[0, g.ny // 2, g.nx // 2:].cpu().numpy() - 1.0  # surface elevation along the positive x half-axis
+    x = g.x_nodes()[g.nx // 2:]
+    res = {"nodes": g.nx * g.ny, "steps": nsteps, "dt": dt, "wall_s": wall,
+           "node_stage_per_s": g.nx * g.ny * 4 * nsteps / wall,
+           "mass_drift_rel": (m1 - m0) / abs(m0), "energy_drift_rel": (e1 - e0) / abs(e0),
+           "energy_drift_rel_to_excess": (e1 - e0) / abs(e0 - e_rest),
+           "max_surface_elevation_on_axis": float(eta.max()),
+           "x_of_max_elevation": float(x[int(np.argmax(eta))])}
+    log(f"[long dam break] {wall:.1f} s, dE/(E - E_rest) = {res['energy_drift_rel_to_excess']:.3e}")
+    s.close()
+    return res
+
+
 def torch_f64():
     import torch
     return torch.float64
@@ -369,6 +419,8 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
+    ap.add_argument("--long-dam-break", action="store_true",
+                    help="also run the 10^8-node cylindrical dam break to t = 300 (several minutes)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -418,6 +470,8 @@ def main():
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
     if "paper" in chosen:
         variants["paper_setups"] = run_paper_setups(P, T)
+    if args.long_dam_break:
+        variants["cylindrical_dam_break_to_t300"] = run_long_dam_break(P, T)
     if "paths" in chosen:
         for other in sorted(PATHS):
             if other != P:
