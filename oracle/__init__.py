@@ -63,6 +63,7 @@ def _load():
         lib.orc_rk4.argtypes = [gp, dp, dp, d, d, ctypes.c_int64, ctypes.c_int]
         lib.orc_rk4_f32.argtypes = [gp, fp, fp, d, d, ctypes.c_int64, ctypes.c_int]
         lib.orc_init_aux.argtypes = [gp, dp, dp]
+        lib.orc_rk4_relax.argtypes = [gp, dp, dp, d, d, ctypes.c_int64, dp, dp]
         lib.orc_mass_energy.argtypes = [gp, dp, dp, dp, dp]
         lib.orc_mass_energy_f32.argtypes = [gp, fp, fp, dp, dp]
         lib.orc_rates.argtypes = [gp, dp, dp, dp, dp, dp]
@@ -174,6 +175,16 @@ def rk4_f32(grid, q, b, dt: float, nsteps: int, t0: float = 0.0, src: int = 0) -
     b = np.ascontiguousarray(b, dtype=np.float32)
     _load().orc_rk4_f32(ctypes.byref(_grid(grid)), _fp(q), _fp(b), dt, t0, nsteps, src)
     return q
+
+
+def rk4_relax(grid, q, b, dt: float, nsteps: int, t0: float = 0.0):
+    """Relaxation RK4 (incremental direction form): returns (q, t_end, gammas)."""
+    q = _state(q, grid).copy()
+    b = _plane(b, grid)
+    t_end = ctypes.c_double()
+    gam = np.zeros(max(int(nsteps), 1))
+    _load().orc_rk4_relax(ctypes.byref(_grid(grid)), _dp(q), _dp(b), dt, t0, int(nsteps), ctypes.byref(t_end), _dp(gam))
+    return q, t_end.value, gam[:nsteps]
 
 
 def init_aux(grid, q, b) -> np.ndarray:

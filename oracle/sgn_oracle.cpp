@@ -405,6 +405,38 @@ double energy_density(double g, double lam, double h, double u, double v, double
   return h * ((u * u + v * v) / 2.0 + e);
 }
 
+// E(q + gam d) - E(q), the change of the total energy along an update
+// direction d, accumulated in extended precision (long double) so that the
+// difference of two totals that agree in their leading digits keeps its own.
+long double energy_change(const orc_grid& gr, const Ops& o, const double* q, const double* d, const double* b,
+                          long double gam) {
+  const size_t N = o.N;
+  const long double g = gr.g, lam = gr.lambda;
+  long double sum = 0.0L, comp = 0.0L;  // Neumaier
+  for (int j = 0; j < o.ny; ++j)
+    for (int i = 0; i < o.nx; ++i) {
+      const size_t k = (size_t)j * o.nx + i;
+      long double x0[5], x1[5];
+      for (int f = 0; f < 5; ++f) {
+        x0[f] = q[f * N + k];
+        x1[f] = x0[f] + gam * (long double)d[f * N + k];
+      }
+      const long double bk = b[k];
+      long double e[2];
+      const long double* xs[2] = {x0, x1};
+      for (int m = 0; m < 2; ++m) {
+        const long double h = xs[m][0], u = xs[m][1], v = xs[m][2], w = xs[m][3], eta = xs[m][4];
+        const long double r = eta / h - 1.0L;
+        e[m] = h * ((u * u + v * v) / 2.0L + w * w / 6.0L + g / 2.0L * (h + 2.0L * bk) + lam / 6.0L * r * r);
+      }
+      const long double x = (long double)o.x.w[i] * (long double)o.y.w[j] * (e[1] - e[0]);
+      const long double t = sum + x;
+      comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+      sum = t;
+    }
+  return sum + comp;
+}
+
 template <class T>
 void init_aux_impl(const Ops& o, T* q, const T* b) {
   const size_t N = o.N;
@@ -745,6 +777,52 @@ void orc_rk4(const orc_grid* g, double* q, const double* b, double dt, double t0
 void orc_rk4_f32(const orc_grid* g, float* q, const float* b, double dt, double t0, int64_t nsteps, int src) {
   Ops o = make_ops(*g);
   for (int64_t s = 0; s < nsteps; ++s) rk4_step_impl<float>(*g, o, q, b, dt, t0 + s * dt, src);
+}
+
+// Relaxation RK4 in the incremental direction form (the fully discrete energy
+// conservation the paper names as an extension): each step computes the
+// classical RK4 update d = q_RK4 - q_n, then q_{n+1} = q_n + gam_n d and
+// t_{n+1} = t_n + gam_n dt, with gam_n the root in [1/2, 3/2] of
+// E(q_n + gam d) = E(q_n) (the other root is gam = 0), found by bisection on the
+// extended-precision energy change.  Without a sign change (d = 0) gam_n = 1.
+// gammas[n] receives gam_n; *t_end the final time.
+void orc_rk4_relax(const orc_grid* g, double* q, const double* b, double dt, double t0, int64_t nsteps,
+                   double* t_end, double* gammas) {
+  Ops o = make_ops(*g);
+  const size_t M = 5 * o.N;
+  std::vector<double> qrk(M), d(M);
+  double t = t0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    std::memcpy(qrk.data(), q, M * sizeof(double));
+    rk4_step_impl<double>(*g, o, qrk.data(), b, dt, t, 0);
+    for (size_t k = 0; k < M; ++k) d[k] = qrk[k] - q[k];
+    long double lo = 0.5L, hi = 1.5L;
+    long double rlo = energy_change(*g, o, q, d.data(), b, lo);
+    const long double rhi = energy_change(*g, o, q, d.data(), b, hi);
+    double gam = 1.0;
+    if ((rlo < 0.0L && rhi > 0.0L) || (rlo > 0.0L && rhi < 0.0L)) {
+      for (int it = 0; it < 80; ++it) {
+        const long double mid = 0.5L * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        const long double rm = energy_change(*g, o, q, d.data(), b, mid);
+        if (rm == 0.0L) {
+          lo = hi = mid;
+          break;
+        }
+        if ((rm < 0.0L) == (rlo < 0.0L)) {
+          lo = mid;
+          rlo = rm;
+        } else {
+          hi = mid;
+        }
+      }
+      gam = (double)(0.5L * (lo + hi));
+    }
+    for (size_t k = 0; k < M; ++k) q[k] = q[k] + gam * d[k];
+    t = t + gam * dt;
+    if (gammas) gammas[s] = gam;
+  }
+  *t_end = t;
 }
 
 void orc_init_aux(const orc_grid* g, double* q, const double* b) {

@@ -140,6 +140,29 @@ def test_step_deterministic():
     assert outs[0][1] == outs[1][1]
 
 
+@pytest.mark.parametrize("path", ["fused", "pairs", "stages"])
+def test_graph_replays_match_direct_launches(path):
+    """sgn_step replays a captured graph of 8 steps; sgn_profile_stages advances
+    the same steps with direct launches.  Several replays, with eager work
+    (rhs, totals, a host copy and synchronizations) between them, must each
+    equal the direct launches bit for bit."""
+    p = W.soliton_over_bathymetry(200, seed=6)
+    q0 = oracle.init_aux(p.grid, p.q0, p.b)
+    dt = 2e-3
+    s = solver(p.grid)
+    s.set_step_path(path)
+    s.set_bathymetry(dev(p.b))
+    g_state = dev(q0)
+    d_state = dev(q0)
+    for rep in range(4):
+        s.step(g_state, dt, 8)            # graph replay
+        s.profile_stages(d_state, dt, 8)  # direct launches of the same 8 steps
+        s.rhs(g_state)                    # eager work between replays
+        s.mass_energy(d_state)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(g_state), host(d_state)), (path, rep)
+
+
 def test_restart_equals_uninterrupted():
     """k steps, copy the state out, continue from the copy == one uninterrupted run (bitwise)."""
     p = W.gaussian_bump_periodic(96, seed=4)
