@@ -63,7 +63,7 @@ STEP_SOURCES_SHA256 = "6b955712b60c964b456bab1ea915af44e06846851033263ad4ff92b12
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
-ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper"}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation"}
 
 
 def log(msg):
@@ -340,6 +340,43 @@ def run_long_dam_break(path, tile_y, t_end=300.0):
     return res
 
 
+def run_relaxation(problem, steps, warmup, path, tile_y):
+    """Relaxation RK4 on the main workload: throughput and energy drift, against
+    classical RK4 over the same steps from the same state."""
+    import torch
+    from paper_2601_02540_amd.binding import Solver
+    grid = problem.grid
+    s = Solver(grid, torch.float64)
+    s.set_step_path(path)
+    if tile_y is not None:
+        s.set_tile_y(tile_y)
+    b = torch.from_numpy(problem.b).cuda()
+    q = torch.from_numpy(problem.q0).cuda()
+    s.set_bathymetry(b)
+    s.init_aux(q)
+    dt = s.cfl_dt(q, 0.5)
+    q_plain = q.clone()
+    _, e0 = s.mass_energy(q)
+    if warmup > 0:
+        s.step_relaxation(q, dt, warmup)
+        s.step(q_plain, dt, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_end = s.step_relaxation(q, dt, steps, warmup * dt)
+    sec = time.perf_counter() - t0
+    s.step(q_plain, dt, steps)
+    _, er = s.mass_energy(q)
+    _, ec = s.mass_energy(q_plain)
+    cells = grid.nx * grid.ny
+    res = {"value": cells * 4 * steps / sec, "ms_per_step": sec / steps * 1e3, "dt": dt,
+           "mean_gamma": (t_end - warmup * dt) / (steps * dt),
+           "energy_drift_rel": (er - e0) / abs(e0), "classical_rk4_energy_drift_rel": (ec - e0) / abs(e0)}
+    log(f"[relaxation] {res['value']:.4e} cell-stage/s  {res['ms_per_step']:.3f} ms/step  "
+        f"dE/E {res['energy_drift_rel']:.2e} (classical {res['classical_rk4_energy_drift_rel']:.2e})")
+    s.close()
+    return res
+
+
 def torch_f64():
     import torch
     return torch.float64
@@ -415,7 +452,8 @@ def main():
     ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
-                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper (default all)")
+                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation "
+                         "(default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
@@ -468,6 +506,8 @@ def main():
         variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
+    if "relaxation" in chosen:
+        variants["relaxation_f64"] = run_relaxation(prob, min(args.steps, 200), 8, P, T)
     if "paper" in chosen:
         variants["paper_setups"] = run_paper_setups(P, T)
     if args.long_dam_break:

@@ -133,10 +133,25 @@ sgn_status sgn_init_aux(sgn_ctx* ctx, void* q);
 sgn_status sgn_rhs(sgn_ctx* ctx, const void* q, void* dq, double t);
 
 /* Advance q in place by nsteps steps of the classical four-stage Runge-Kutta
- * method with fixed step dt, starting at time t0.  Each stage is one fused
- * kernel (right-hand side plus the stage update).  nsteps == 0 is a no-op.
- * Without a source the steps are replayed from a captured HIP graph. */
+ * method with fixed step dt, starting at time t0, on the context's step path
+ * (SGN_OPT_STEP_PATH).  nsteps == 0 is a no-op.  Without a source the steps
+ * are replayed from a captured HIP graph. */
 sgn_status sgn_step(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0);
+
+/* Relaxation RK4 (fully discrete energy conservation; the extension the paper
+ * names in its conclusions).  Each step takes the classical RK4 update
+ * d = q_RK4 - q_n (computed on the context's step path into the context's
+ * scratch state) and sets q_{n+1} = q_n + gam_n d, t_{n+1} = t_n + gam_n dt, with
+ * gam_n the root near 1 of E(q_n + gam d) = E(q_n), E the total energy of
+ * Theorem 2.  Since the semi-discretization conserves E, the fully discrete E
+ * is then conserved to rounding and the method keeps fourth order in time.
+ * gam_n comes from two Newton iterations from 1 on the device (FP64 reductions,
+ * no host synchronization per step; steps are replayed from a captured graph);
+ * a step without a root in [1/2, 3/2] keeps gam = 1.  The state stays in q.
+ * If t_end is not NULL it receives t0 + sum_n gam_n dt (synchronizes, and
+ * reports the health flag); otherwise the call is asynchronous.  Requires no
+ * source term (SGN_E_UNSUPPORTED). */
+sgn_status sgn_step_relaxation(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0, double* t_end);
 
 /* Total mass 1^T M h (FP64 result, compensated deterministic summation). */
 sgn_status sgn_mass(sgn_ctx* ctx, const void* q, double* out);

@@ -91,6 +91,7 @@ def load_library() -> ctypes.CDLL:
         "sgn_batch_mass_energy": ([vp, dp, dp], st),
         "sgn_batch_cfl_dt": ([vp, d, dp], st),
         "sgn_batch_set_tiling": ([vp, ctypes.c_int32, ctypes.c_int32], st),
+        "sgn_step_relaxation": ([vp, vp, d, ctypes.c_int64, d, dp], st),
         "sgn_batch_set_step_path": ([vp, ctypes.c_int32], st),
         "sgn_batch_autotune": ([vp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp], st),
         "sgn_batch_check": ([vp, ctypes.POINTER(ctypes.c_int32)], st),
@@ -215,6 +216,13 @@ class Solver:
     def step(self, q, dt: float, nsteps: int = 1, t0: float = 0.0):
         self._chk(self.lib.sgn_step(self.ctx, self._state(q), float(dt), int(nsteps), float(t0)))
         return q
+
+    def step_relaxation(self, q, dt: float, nsteps: int = 1, t0: float = 0.0) -> float:
+        """Relaxation RK4 steps in place; returns the final time t0 + sum gam_n dt."""
+        t_end = ctypes.c_double()
+        self._chk(self.lib.sgn_step_relaxation(self.ctx, self._state(q), float(dt), int(nsteps), float(t0),
+                                               ctypes.byref(t_end)))
+        return t_end.value
 
     def mass_energy(self, q) -> Tuple[float, float]:
         m, e = ctypes.c_double(), ctypes.c_double()

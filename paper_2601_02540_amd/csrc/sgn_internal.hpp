@@ -60,6 +60,7 @@ struct sgn_ctx {
   int tile_y = 8;     // stage and pair kernels
   int step_tile = 16;  // step kernel: 16 selects 32 x 16, 8 selects 64 x 8
   sgn_host::GraphCache graphs[2];
+  sgn_host::GraphCache relax_graph;  // relaxation steps (sgn_step_relaxation)
   sgn_host::AdjointBuffers adj;
   std::string err;
 };

@@ -56,6 +56,8 @@ void destroy_graphs(sgn_ctx* c) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     g = GraphCache{};
   }
+  if (c->relax_graph.exec) (void)hipGraphExecDestroy(c->relax_graph.exec);
+  c->relax_graph = GraphCache{};
 }
 
 int reduce_blocks(const sgn_ctx* c) { return c->p.ny < sgn::RED_MAX_BLOCKS ? c->p.ny : sgn::RED_MAX_BLOCKS; }
