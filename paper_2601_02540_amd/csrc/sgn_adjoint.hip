@@ -18,7 +18,7 @@ using sgn_host::fail;
 using sgn_host::hip_fail;
 #define HIPCHK(c, expr) SGN_HIPCHK(c, expr)
 
-constexpr int VJP_TY = 4;
+constexpr int VJP_TY = 8;
 
 template <typename T, int ROLE>
 hipError_t launch_vjp_t(const sgn_ctx* c, hipStream_t s, const void* Y, const void* Kin, void* Qb, void* Kout,
