@@ -463,7 +463,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (the kernels are measured on one GPU's share); "
+                                   "--gpus must be 1",
                           "requested_gpus": args.gpus}), flush=True)
         sys.exit(2)
 

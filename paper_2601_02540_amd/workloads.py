@@ -114,7 +114,7 @@ def random_phase_bathymetry(grid: Grid, rng: np.random.Generator, amp: float = 0
                             kmax: int = 8) -> np.ndarray:
     """b = amp * S / max|S|, S = sum_{(m,n) != 0, |m|,|n| <= kmax} (m^2+n^2)^-1 cos(2 pi (m x / Lx + n y / Ly) + phi_mn).
 
-    Integer wave numbers make b periodic on the box.
+    Integer wave numbers make b periodic on the square domain.
     """
     Lx = grid.xmax - grid.xmin
     Ly = grid.ymax - grid.ymin

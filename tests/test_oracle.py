@@ -264,7 +264,7 @@ def test_transpose_symmetry(bc):
 
 
 def test_mirror_symmetry():
-    """Reflecting box mirrored in x (x -> -x, u -> -u) gives the mirrored rates."""
+    """A reflecting domain mirrored in x (x -> -x, u -> -u) gives the mirrored rates."""
     g = W.Grid(9, 7, -1.0, 1.0, 0.0, 3.0, REF, REF, 9.81, 500.0)
     q, b = W.random_state(g, 8)
     qm = q[:, :, ::-1].copy()
