@@ -264,9 +264,10 @@ sgn_status sgn_batch_cfl_dt(sgn_batch* batch, double cfl, double* dt);
  * Resets the tile height to the path's default (16; pairs in SGN_F64: 8). */
 sgn_status sgn_batch_set_step_path(sgn_batch* batch, int32_t path);
 /* Tile height (8 or 16; on the fused path 8 selects 64 x 8 tiles and 16
- * selects 32 x 16) and persistent workgroups per compute unit (1..16). */
+ * selects 32 x 16) and persistent workgroups per compute unit (1..16), or 0
+ * for one workgroup per tile (no persistent loop; fewer registers). */
 sgn_status sgn_batch_set_tiling(sgn_batch* batch, int32_t tile_y, int32_t blocks_per_cu);
-/* Time every (tile height 8 or 16, 1..6 workgroups per CU) candidate of the
+/* Time every (tile height 8 or 16, 0..6 workgroups per CU) candidate of the
  * current step path on one step from the
  * registered states into scratch (the states are read, never written), keep
  * the fastest and report it (any output may be NULL; ms = time of one step).

@@ -131,15 +131,23 @@ int persistent_grid(const sgn_batch* b, int bpc) {
   return std::max(8, std::min(grid, maxgrid));
 }
 
+// blocks_per_cu 0 selects one workgroup per work item, else a persistent grid.
+template <typename T, int PAIR, int TY>
+void launch_batch_pair_k(const sgn_batch* b, hipStream_t s, int parity, int bpc) {
+  if (bpc == 0)
+    hipLaunchKernelGGL((sgn::batch_pair_kernel<T, PAIR, TY, false>), dim3(b->nwork), dim3(sgn::STAGE_THREADS), 0, s,
+                       b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+  else
+    hipLaunchKernelGGL((sgn::batch_pair_kernel<T, PAIR, TY, true>), dim3(persistent_grid(b, bpc)),
+                       dim3(sgn::STAGE_THREADS), 0, s, b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+}
+
 template <typename T, int TY>
 hipError_t launch_batch_pair_t(const sgn_batch* b, hipStream_t s, int pair, int parity, int bpc) {
-  const int grid = persistent_grid(b, bpc);
   if (pair == 1)
-    hipLaunchKernelGGL((sgn::batch_pair_kernel<T, 1, TY>), dim3(grid), dim3(sgn::STAGE_THREADS), 0, s, b->d_desc,
-                       b->d_work, b->nwork, parity, b->d_flags);
+    launch_batch_pair_k<T, 1, TY>(b, s, parity, bpc);
   else
-    hipLaunchKernelGGL((sgn::batch_pair_kernel<T, 2, TY>), dim3(grid), dim3(sgn::STAGE_THREADS), 0, s, b->d_desc,
-                       b->d_work, b->nwork, parity, b->d_flags);
+    launch_batch_pair_k<T, 2, TY>(b, s, parity, bpc);
   return hipGetLastError();
 }
 
@@ -153,8 +161,12 @@ hipError_t launch_batch_pair(const sgn_batch* b, hipStream_t s, int pair, int pa
 
 template <typename T, int TX>
 hipError_t launch_batch_step_t(const sgn_batch* b, hipStream_t s, int parity, int bpc) {
-  hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX>), dim3(persistent_grid(b, bpc)), dim3(sgn::STAGE_THREADS), 0, s,
-                     b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+  if (bpc == 0)
+    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX, false>), dim3(b->nwork), dim3(sgn::STAGE_THREADS), 0, s,
+                       b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+  else
+    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX, true>), dim3(persistent_grid(b, bpc)), dim3(sgn::STAGE_THREADS),
+                       0, s, b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
   return hipGetLastError();
 }
 
@@ -485,7 +497,7 @@ sgn_status sgn_batch_set_step_path(sgn_batch* b, int32_t path) {
 sgn_status sgn_batch_set_tiling(sgn_batch* b, int32_t tile_y, int32_t blocks_per_cu) {
   if (!b) return SGN_E_ARG;
   if (tile_y != 8 && tile_y != 16) return bfail(b, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
-  if (blocks_per_cu < 1 || blocks_per_cu > 16) return bfail(b, SGN_E_ARG, "blocks per CU must be in [1, 16]");
+  if (blocks_per_cu < 0 || blocks_per_cu > 16) return bfail(b, SGN_E_ARG, "blocks per CU must be in [0, 16]");
   b->tile_y = tile_y;
   b->blocks_per_cu = blocks_per_cu;
   drop_graph(b);
@@ -506,7 +518,7 @@ sgn_status sgn_batch_autotune(sgn_batch* b, const double* dt, int32_t* tile_y, i
   // Candidates are timed on one step from q into the scratch buffer (parity 0),
   // which reads the states but never writes them.
   const int tys[2] = {8, 16};
-  const int bpcs[6] = {1, 2, 3, 4, 5, 6};
+  const int bpcs[7] = {0, 1, 2, 3, 4, 5, 6};
   double best = 1e300;
   int best_ty = b->tile_y, best_bpc = b->blocks_per_cu;
   hipEvent_t e0, e1;

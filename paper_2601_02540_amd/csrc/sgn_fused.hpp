@@ -15,8 +15,9 @@
 // kernels.  The price is the ring evaluations (48 wave evaluations per tile and
 // step for a 64 x 8 tile, 44 for 32 x 16, against 32 without rings).
 //
-// Thread map: thread t owns the tile nodes t and t + 256 (row-major in the
-// tile) in every stage, so their q and acc stay in registers.  Ring nodes are
+// Thread map: thread t owns the two tile nodes (t mod TX, 2 floor(t / TX) + k),
+// k = 0, 1, in every stage, so their q and acc stay in registers; the pair
+// shares two of its y-neighbours.  Ring nodes are
 // numbered by distance (all of ring 1 first, then ring 2, then ring 3); thread
 // t evaluates ring nodes t and t + 256 in every stage whose region contains
 // them, so the q of a ring node is read from LDS once, in the first stage.
@@ -58,6 +59,16 @@ template <typename T, int TX, int PAD>
 struct StepSmem {
   T f[7][StepGeom<TX>::RY][StepGeom<TX>::RX + PAD];  // h u v w eta b 1/h, then the current stage (b kept)
 };
+
+// The node's values behind an empty asm statement: the compiler can no longer
+// identify them with the values they were copied from, so it neither merges
+// arithmetic on them with earlier arithmetic nor changes how that arithmetic
+// is fused.
+template <typename T>
+__device__ __forceinline__ Node<T> opaque_node(Node<T> n) {
+  asm volatile("" : "+v"(n.h), "+v"(n.u), "+v"(n.v), "+v"(n.w), "+v"(n.eta), "+v"(n.b), "+v"(n.ih));
+  return n;
+}
 
 // Position (r, c), relative to the tile origin, of ring node m (0 <= m < RING3).
 template <int TX>
@@ -141,14 +152,14 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     }
   }
 
-  // Owned nodes (lx, ly[k]) and ring slots of this thread.
+  // Owned nodes (lx, ly0 + k), k = 0, 1, and ring slots of this thread.
   const int lx = tid % TX;
-  const int ly0 = tid / TX;
+  const int ly0 = 2 * (tid / TX);
   const int i = i0 + lx;
   bool own_dom[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const int j = j0 + ly0 + k * G::ROWS;
+    const int j = j0 + ly0 + k;
     own_dom[k] = on_axis<BCX>(i, nx) && on_axis<BCY>(j, ny);
   }
   int ring_r[2], ring_c[2];
@@ -175,15 +186,12 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     const double ts = t0 + (st == 1 ? 0.0 : (st == 4 ? dt : 0.5 * dt));
     const int ring_lim = st == 1 ? G::RING3 : (st == 2 ? G::RING2 : G::RING1);
     T ro[2][5], rr[2][5];
-    // owned nodes
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      __builtin_amdgcn_sched_barrier(0);
-      const int ly = ly0 + k * G::ROWS;
-      const int j = j0 + ly;
-      if (st < 4 ? !own_dom[k] : (i >= nx || j >= ny)) continue;
-      Node<T> cn;
-      const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ly + STEP_HALO, lx + STEP_HALO, i, j, gc, ts, cn);
+    // Owned nodes.  Node 1 lies just above node 0 in y, so whenever node 1 is
+    // in the domain (then j0 + ly0 + 1 is neither the first row nor beyond the
+    // last) its centre is node 0's upper y-neighbour and its lower
+    // y-neighbour is node 0's centre: the pair reads 8 nodes from LDS, not 10.
+    const auto finish = [&](int k, const Rates<T>& kk, const Node<T>& cn) {
+      const int j = j0 + ly0 + k;
       const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
       if (st == 1) {
         const T yv[5] = {cn.h, cn.u, cn.v, cn.w, cn.eta};
@@ -217,6 +225,38 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
         const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
         if (!isfinite(sum)) health |= FLAG_NONFINITE;
       }
+    };
+    {
+      __builtin_amdgcn_sched_barrier(0);
+      const int j = j0 + ly0;
+      // node 1 in the domain implies node 0 in the domain
+      const bool run0 = st < 4 ? own_dom[0] : (i < nx && j < ny);
+      const bool run1 = st < 4 ? own_dom[1] : (i < nx && j + 1 < ny);
+      if (run0) {
+        const int r = ly0 + STEP_HALO, c = lx + STEP_HALO;
+        const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
+        const AxisStencil<BCY> ay0(j, ny, gc.inv2dy, gc.invdy);
+        const Node<T> c0 = lds_load<T>(s, r, c);
+        const Node<T> up = lds_load<T>(s, r + ay0.op, c);
+        {
+          const Node<T> xm = lds_load<T>(s, r, c + ax.om);
+          const Node<T> xp = lds_load<T>(s, r, c + ax.op);
+          const Node<T> dn = lds_load<T>(s, r + ay0.om, c);
+          finish(0, node_rates<T, BCX, BCY, SRC>(c0, xm, xp, dn, up, ax, ay0, i, j, gc, ts), c0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (run1) {
+          // Node 1 re-enters the shared nodes as opaque values: products of
+          // them formed for node 0 are formed again, rounded exactly as every
+          // other evaluation of the right-hand side rounds them.
+          const Node<T> c0n = opaque_node(c0), upn = opaque_node(up);
+          const AxisStencil<BCY> ay1(j + 1, ny, gc.inv2dy, gc.invdy);
+          const Node<T> xm = lds_load<T>(s, r + 1, c + ax.om);
+          const Node<T> xp = lds_load<T>(s, r + 1, c + ax.op);
+          const Node<T> up1 = lds_load<T>(s, r + 1 + ay1.op, c);
+          finish(1, node_rates<T, BCX, BCY, SRC>(upn, xm, xp, c0n, up1, ax, ay1, i, j + 1, gc, ts), upn);
+        }
+      }
     }
     if (st == 4) break;
     // ring nodes inside this stage's region
@@ -244,7 +284,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       if (!own_dom[k]) continue;
-      const int r = ly0 + k * G::ROWS + STEP_HALO, c = lx + STEP_HALO;
+      const int r = ly0 + k + STEP_HALO, c = lx + STEP_HALO;
 #pragma unroll
       for (int f = 0; f < 5; ++f) s.f[f][r][c] = ro[k][f];
       s.f[6][r][c] = T(1) / ro[k][0];

@@ -46,13 +46,28 @@ __device__ __forceinline__ bool on_axis(int g, int n) {
   return g >= 0 && g < n;
 }
 
-// Right-hand side at LDS position (r, c) of node (i, j) (unwrapped indices).
-// `Smem` holds the planes h u v w eta b 1/h as f[7][rows][cols].
-template <typename T, int BCX, int BCY, bool SRC, class Smem>
-__device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i, int j, const GridConst& gc, double t,
-                                              Node<T>& center) {
-  const AxisStencil<BCX> ax(i, gc.nx, gc.inv2dx, gc.invdx);
-  const AxisStencil<BCY> ay(j, gc.ny, gc.inv2dy, gc.invdy);
+// The seven staged values of LDS position (r, c).  `Smem` holds the planes
+// h u v w eta b 1/h as f[7][rows][cols].
+template <typename T, class Smem>
+__device__ __forceinline__ Node<T> lds_load(const Smem& s, int r, int c) {
+  Node<T> n;
+  n.h = s.f[0][r][c];
+  n.u = s.f[1][r][c];
+  n.v = s.f[2][r][c];
+  n.w = s.f[3][r][c];
+  n.eta = s.f[4][r][c];
+  n.b = s.f[5][r][c];
+  n.ih = s.f[6][r][c];
+  return n;
+}
+
+// Right-hand side at node (i, j) (unwrapped indices) from its value and its four
+// neighbours as the stencils ax, ay select them (closure rows included).
+template <typename T, int BCX, int BCY, bool SRC>
+__device__ __forceinline__ Rates<T> node_rates(const Node<T>& center, const Node<T>& xm, const Node<T>& xp,
+                                               const Node<T>& ym, const Node<T>& yp, const AxisStencil<BCX>& ax,
+                                               const AxisStencil<BCY>& ay, int i, int j, const GridConst& gc,
+                                               double t) {
   T satx = T(0), saty = T(0);
   if (BCX == BC_REFLECTING) {
     if (i == 0) satx = T(-2.0 * gc.invdx);
@@ -62,29 +77,8 @@ __device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i
     if (j == 0) saty = T(-2.0 * gc.invdy);
     if (j == gc.ny - 1) saty = T(2.0 * gc.invdy);
   }
-  center.h = s.f[0][r][c];
-  center.u = s.f[1][r][c];
-  center.v = s.f[2][r][c];
-  center.w = s.f[3][r][c];
-  center.eta = s.f[4][r][c];
-  center.b = s.f[5][r][c];
-  center.ih = s.f[6][r][c];
-  Node<T> xm, xp, ym, yp;
-  const int cm = c + ax.om, cp = c + ax.op, rm = r + ay.om, rp = r + ay.op;
-#define SGN_LD(N, R, C)     \
-  N.h = s.f[0][R][C];       \
-  N.u = s.f[1][R][C];       \
-  N.v = s.f[2][R][C];       \
-  N.w = s.f[3][R][C];       \
-  N.eta = s.f[4][R][C];     \
-  N.b = s.f[5][R][C];       \
-  N.ih = s.f[6][R][C];
-  SGN_LD(xm, r, cm)
-  SGN_LD(xp, r, cp)
-  SGN_LD(ym, rm, c)
-  SGN_LD(yp, rp, c)
-#undef SGN_LD
-  Rates<T> k = split_form_rates<T, BCX, BCY>(center, xm, xp, ym, yp, T(ax.scale), T(ay.scale), T(gc.g), T(gc.lam), satx, saty);
+  Rates<T> k = split_form_rates<T, BCX, BCY>(center, xm, xp, ym, yp, T(ax.scale), T(ay.scale), T(gc.g), T(gc.lam),
+                                             satx, saty);
   if (SRC) {
     const int gi = wrap_or_clamp<BCX>(i, gc.nx), gj = wrap_or_clamp<BCY>(j, gc.ny);
     double S[5];
@@ -96,6 +90,20 @@ __device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i
     k.eta += T(S[4]);
   }
   return k;
+}
+
+// Right-hand side at LDS position (r, c) of node (i, j) (unwrapped indices).
+template <typename T, int BCX, int BCY, bool SRC, class Smem>
+__device__ __forceinline__ Rates<T> tile_eval(const Smem& s, int r, int c, int i, int j, const GridConst& gc, double t,
+                                              Node<T>& center) {
+  const AxisStencil<BCX> ax(i, gc.nx, gc.inv2dx, gc.invdx);
+  const AxisStencil<BCY> ay(j, gc.ny, gc.inv2dy, gc.invdy);
+  center = lds_load<T>(s, r, c);
+  const Node<T> xm = lds_load<T>(s, r, c + ax.om);
+  const Node<T> xp = lds_load<T>(s, r, c + ax.op);
+  const Node<T> ym = lds_load<T>(s, r + ay.om, c);
+  const Node<T> yp = lds_load<T>(s, r + ay.op, c);
+  return node_rates<T, BCX, BCY, SRC>(center, xm, xp, ym, yp, ax, ay, i, j, gc, t);
 }
 
 // One tile (origin i0, j0) of a stage pair, executed by a whole workgroup.

@@ -53,10 +53,12 @@ def run_batch(probs, dtype, dts, nsteps, tiling=None, path=None):
 @pytest.mark.parametrize("path", ["fused", "pairs"])
 @pytest.mark.parametrize("dtype,ty", [(torch.float64, 8), (torch.float64, 16), (torch.float32, 16)])
 @pytest.mark.parametrize("nsteps", [1, 2, 11])
-def test_batch_equals_single_solver(path, dtype, ty, nsteps):
+@pytest.mark.parametrize("bpc", [0, 2])
+def test_batch_equals_single_solver(path, dtype, ty, nsteps, bpc):
+    """bpc 0: one workgroup per tile; 2: a persistent grid."""
     probs = small_ensemble()
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
-    _, outs = run_batch(probs, dtype, dts, nsteps, (ty, 2), path)
+    _, outs = run_batch(probs, dtype, dts, nsteps, (ty, bpc), path)
     for (g, q, b), dt, got in zip(probs, dts, outs):
         s = Solver(g, dtype)
         s.set_step_path(path)
@@ -97,7 +99,7 @@ def test_batch_autotune_reads_states_only():
     batch.set_states(qs)
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
     ty, bpc, ms = batch.autotune(dts)
-    assert ty in (8, 16) and 1 <= bpc <= 6 and ms > 0
+    assert ty in (8, 16) and 0 <= bpc <= 6 and ms > 0
     for q, p in zip(qs, probs):
         assert np.array_equal(host(q), p[1])
     batch.step(dts, 2)

@@ -282,6 +282,7 @@ def test_step_paths_and_tiles(shape, bcs):
     q[1:4] *= 0.1
     dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
     ref3 = oracle.rk4(g, q, b, dt, 3)
+    outs = []
     for path in PATHS:
         for ty in (8, 16):
             s = solver(g)
@@ -290,8 +291,12 @@ def test_step_paths_and_tiles(shape, bcs):
             s.set_bathymetry(dev(b))
             qd = dev(q)
             s.step(qd, dt, 3)  # a double step then an odd single step on the pair and fused paths
-            err = field_rel_err(host(qd), ref3, STATE_FLOORS)
+            outs.append(host(qd))
+            err = field_rel_err(outs[-1], ref3, STATE_FLOORS)
             assert np.all(err <= F64_TOL), (path, ty, err)
+    # every path and tile shape forms the same values
+    for k, o in enumerate(outs[1:]):
+        assert np.array_equal(o, outs[0]), k + 1
 
 
 @pytest.mark.parametrize("bc", [PER, REF])
