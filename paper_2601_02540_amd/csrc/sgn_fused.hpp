@@ -28,6 +28,7 @@
 #pragma once
 
 #include "sgn_pair.hpp"
+#include "sgn_reduce.hpp"
 
 namespace sgn {
 
@@ -104,12 +105,16 @@ __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
 // One tile (origin i0, j0) of one RK4 step, executed by a whole workgroup.
 // SAVE (the adjoint's recomputation): also write the intermediate stages
 // Y2, Y3, Y4 of the owned nodes to ysave, three consecutive states.
+// RELAX (relaxation RK4): also reduce the tile's sums of M s(1) and M s'(1)
+// (relax_node_terms at gam = 1, from the step's input and output values held
+// in registers) into rpart[0..3] (compensated: sum, error, sum, error).
 // The caller synchronizes the workgroup before reusing `s` for another tile.
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD>
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, bool RELAX = false>
 __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridConst& gc, int i0, int j0,
                                           const T* __restrict__ q, const T* __restrict__ bplane,
                                           T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
-                                          int* __restrict__ flag, T* __restrict__ ysave) {
+                                          int* __restrict__ flag, T* __restrict__ ysave,
+                                          double* __restrict__ rpart = nullptr) {
   using G = StepGeom<TX>;
   constexpr int RX = G::RX;
   constexpr int REGION = G::RX * G::RY;
@@ -179,6 +184,11 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
 
   T qo[2][5], acc[2][5], qr[2][5];
   int health = 0;
+  CSum rsum[2];
+  if (RELAX) {
+    rsum[0].init();
+    rsum[1].init();
+  }
 #pragma unroll
   for (int st = 1; st <= 4; ++st) {
     const T cy = st == 3 ? c1 : c2;     // Y_{st+1} = q + cy k_st
@@ -224,6 +234,19 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
         if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
         const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
         if (!isfinite(sum)) health |= FLAG_NONFINITE;
+        if (RELAX) {
+          double x[5], d[5];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) {
+            x[f] = (double)qo[k][f];
+            d[f] = (double)nv[f] - x[f];
+          }
+          double sv, dsv;
+          relax_node_terms(x, d, (double)s.f[5][ly0 + k + STEP_HALO][lx + STEP_HALO], gc.g, gc.lam, 1.0, sv, dsv);
+          const double M = axis_weight(i, nx, gc.bc_x, gc.dx) * axis_weight(j, ny, gc.bc_y, gc.dy);
+          rsum[0].add(M * sv);
+          rsum[1].add(M * dsv);
+        }
       }
     };
     {
@@ -301,20 +324,32 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     __syncthreads();
   }
   if (health) atomicOr(flag, health);
+  if (RELAX) {
+    block_merge<2>(rsum);
+    if (tid == 0) {
+      rpart[0] = rsum[0].s;
+      rpart[1] = rsum[0].c;
+      rpart[2] = rsum[1].s;
+      rpart[3] = rsum[1].c;
+    }
+  }
 }
 
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false>
+// RELAX: rpart holds 4 doubles per tile, in tile order.
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false, bool RELAX = false>
 __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
                                                              const T* __restrict__ bplane, T* __restrict__ qout,
                                                              T c6, T c3, T c2, T c1, double t0, double dt,
-                                                             int* __restrict__ flag, T* __restrict__ ysave) {
+                                                             int* __restrict__ flag, T* __restrict__ ysave,
+                                                             double* __restrict__ rpart) {
   constexpr int TY = StepGeom<TX>::TY;
   __shared__ StepSmem<T, TX, SRC ? 0 : 1> s;
   const int ntx = (gc.nx + TX - 1) / TX;
   const int nty = (gc.ny + TY - 1) / TY;
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  step_tile<T, BCX, BCY, SRC, TX, SAVE>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane, qout, c6, c3, c2,
-                                        c1, t0, dt, flag, ysave);
+  step_tile<T, BCX, BCY, SRC, TX, SAVE, SRC ? 0 : 1, RELAX>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane,
+                                                            qout, c6, c3, c2, c1, t0, dt, flag, ysave,
+                                                            RELAX ? rpart + 4 * tile : nullptr);
 }
 
 }  // namespace sgn

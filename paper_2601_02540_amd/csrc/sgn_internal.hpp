@@ -51,6 +51,8 @@ struct sgn_ctx {
   void* ya = nullptr;
   void* yb = nullptr;
   double* partials = nullptr;
+  double* relax_partials = nullptr;  // 4 doubles per step tile (relaxation on the step kernel)
+  size_t relax_partials_cap = 0;     // doubles allocated there
   double* result = nullptr;
   double* host_result = nullptr;
   int* flag = nullptr;
@@ -79,9 +81,13 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t);
 // One RK4 step by the step kernel from `cur` into `oth` (distinct buffers);
 // with `ysave` non-null the stage states Y2, Y3, Y4 go to three consecutive
-// state slots there (no source terms).
+// state slots there; with `rpart` non-null each tile's relaxation sums at
+// gam = 1 go to rpart[4 tile ..] (step_tiles(c) tiles).  Neither with source
+// terms, and not both.
 hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
-                             void* ysave);
+                             void* ysave, double* rpart = nullptr);
+// Number of tiles of the step kernel in the current tile shape.
+int step_tiles(const sgn_ctx* c);
 
 }  // namespace sgn_host
 

@@ -151,7 +151,7 @@ hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const v
 
 template <typename T, int TX>
 hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
-                           void* ysave) {
+                           void* ysave, double* rpart) {
   constexpr int TY = sgn::STEP_NODES / TX;
   const int ntx = (c->p.nx + TX - 1) / TX;
   const int nty = (c->p.ny + TY - 1) / TY;
@@ -161,16 +161,21 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
   const T* bp = (const T*)c->b;
   T* op = (T*)qout;
   T* ys = (T*)ysave;
-#define SGN_LAUNCH_K(BX, BY, S, SV)                                                                             \
-  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV>), grid, block, 0, s, c->gc, qp, bp, op,           \
-                     (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys)
-#define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false)
+#define SGN_LAUNCH_K(BX, BY, S, SV, RX)                                                                         \
+  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,       \
+                     (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys, rpart)
+#define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false, false)
   const int bx = c->p.bc_x, by = c->p.bc_y;
-  if (ys) {  // stage saving (no source terms)
-    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true);
-    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true);
-    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true);
-    else SGN_LAUNCH_K(1, 1, false, true);
+  if (rpart) {  // relaxation partial sums (no source terms, no stage saving)
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, false, true);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, false, true);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, false, true);
+    else SGN_LAUNCH_K(1, 1, false, false, true);
+  } else if (ys) {  // stage saving (no source terms)
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true, false);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true, false);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true, false);
+    else SGN_LAUNCH_K(1, 1, false, true, false);
   } else if (!src) {
     if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
     else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
@@ -188,15 +193,16 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 }
 
 // One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct);
-// with `ysave`, also the stage states Y2, Y3, Y4 (three consecutive states).
+// with `ysave`, also the stage states Y2, Y3, Y4 (three consecutive states);
+// with `rpart`, also the relaxation sums of every tile.
 hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
-                        void* ysave = nullptr) {
+                        void* ysave = nullptr, double* rpart = nullptr) {
   if (c->p.dtype == SGN_F64) {
-    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave);
-    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave);
+    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave, rpart);
+    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave, rpart);
   }
-  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave);
-  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave);
+  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave, rpart);
+  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave, rpart);
 }
 
 // Two RK4 steps on the fused path: q -> acc -> q.
@@ -327,8 +333,14 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
 }
 
 hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
-                             void* ysave) {
-  return ::launch_fused(c, s, cur, oth, dt, t, ysave);
+                             void* ysave, double* rpart) {
+  return ::launch_fused(c, s, cur, oth, dt, t, ysave, rpart);
+}
+
+int step_tiles(const sgn_ctx* c) {
+  const int tx = c->step_tile == 16 ? 32 : 64;
+  const int ty = sgn::STEP_NODES / tx;
+  return ((c->p.nx + tx - 1) / tx) * ((c->p.ny + ty - 1) / ty);
 }
 
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {
@@ -455,6 +467,7 @@ sgn_status sgn_destroy(sgn_ctx* c) {
   if (c->ya) (void)hipFree(c->ya);
   if (c->yb) (void)hipFree(c->yb);
   if (c->partials) (void)hipFree(c->partials);
+  if (c->relax_partials) (void)hipFree(c->relax_partials);
   if (c->result) (void)hipFree(c->result);
   if (c->flag) (void)hipFree(c->flag);
   if (c->host_result) (void)hipHostFree(c->host_result);

@@ -17,6 +17,32 @@ namespace sgn {
 constexpr int RED_THREADS = 256;
 constexpr int RED_MAX_BLOCKS = 1024;
 
+// Relaxation RK4: one node's s(gam) = (e(q + gam d) - e(q)) / gam of the energy
+// density e and its derivative s'(gam), from the node's values x, increments d
+// and bottom b.  Each part of e is written out as a polynomial in gam (rational
+// for the lambda term), so the difference is never formed by subtraction.
+__device__ __forceinline__ void relax_node_terms(const double (&x)[5], const double (&dx)[5], double bb, double g,
+                                                 double lam, double gam, double& s, double& ds) {
+  const double h = x[0], u = x[1], v = x[2], w = x[3], eta = x[4], b = bb;
+  const double dh = dx[0], du = dx[1], dv = dx[2], dw = dx[3], deta = dx[4];
+  const double H = h + gam * dh;
+  const double lin_uv = 2.0 * u * du + 2.0 * v * dv, sq_uv = du * du + dv * dv;
+  const double lin_w = 2.0 * w * dw, sq_w = dw * dw;
+  const double A = eta - h, B = deta - dh;
+  const double Nl = h * (2.0 * A * B + gam * B * B) - dh * A * A;
+  const double s_kin = 0.5 * (dh * (u * u + v * v) + H * (lin_uv + gam * sq_uv));
+  const double s_w = (1.0 / 6.0) * (dh * w * w + H * (lin_w + gam * sq_w));
+  const double s_pot = 0.5 * g * dh * (2.0 * h + 2.0 * b + gam * dh);
+  const double ihH2 = 1.0 / (h * H * H);  // one division for both lambda terms
+  const double s_lam = (lam / 6.0) * (Nl * H) * ihH2;
+  const double d_kin = 0.5 * (dh * (lin_uv + gam * sq_uv) + H * sq_uv);
+  const double d_w = (1.0 / 6.0) * (dh * (lin_w + gam * sq_w) + H * sq_w);
+  const double d_pot = 0.5 * g * dh * dh;
+  const double d_lam = (lam / 6.0) * (h * B * B * H - Nl * dh) * ihH2;
+  s = s_kin + s_w + s_pot + s_lam;
+  ds = d_kin + d_w + d_pot + d_lam;
+}
+
 __device__ __forceinline__ void wave_merge(CSum& a) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {

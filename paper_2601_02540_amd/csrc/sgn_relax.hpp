@@ -51,23 +51,10 @@ __global__ __launch_bounds__(RED_THREADS) void relax_partial(const GridConst gc,
         x[f] = (double)q[f * N + o];
         dx[f] = (double)qrk[f * N + o] - x[f];
       }
-      const double h = x[0], u = x[1], v = x[2], w = x[3], eta = x[4], b = (double)bplane[o];
-      const double dh = dx[0], du = dx[1], dv = dx[2], dw = dx[3], deta = dx[4];
-      const double H = h + gam * dh;
-      const double lin_uv = 2.0 * u * du + 2.0 * v * dv, sq_uv = du * du + dv * dv;
-      const double lin_w = 2.0 * w * dw, sq_w = dw * dw;
-      const double A = eta - h, B = deta - dh;
-      const double Nl = h * (2.0 * A * B + gam * B * B) - dh * A * A;
-      const double s_kin = 0.5 * (dh * (u * u + v * v) + H * (lin_uv + gam * sq_uv));
-      const double s_w = (1.0 / 6.0) * (dh * w * w + H * (lin_w + gam * sq_w));
-      const double s_pot = 0.5 * g * dh * (2.0 * h + 2.0 * b + gam * dh);
-      const double s_lam = (lam / 6.0) * Nl / (h * H);
-      const double d_kin = 0.5 * (dh * (lin_uv + gam * sq_uv) + H * sq_uv);
-      const double d_w = (1.0 / 6.0) * (dh * (lin_w + gam * sq_w) + H * sq_w);
-      const double d_pot = 0.5 * g * dh * dh;
-      const double d_lam = (lam / 6.0) * (h * B * B * H - Nl * dh) / (h * H * H);
-      a[0].add(M * (s_kin + s_w + s_pot + s_lam));
-      a[1].add(M * (d_kin + d_w + d_pot + d_lam));
+      double sv, dsv;
+      relax_node_terms(x, dx, (double)bplane[o], g, lam, gam, sv, dsv);
+      a[0].add(M * sv);
+      a[1].add(M * dsv);
     }
   }
   block_merge<2>(a);
@@ -89,9 +76,24 @@ static __global__ __launch_bounds__(RED_THREADS) void relax_newton(const double*
   CSum a[2];
   a[0].init();
   a[1].init();
-  for (int p = threadIdx.x; p < nparts; p += RED_THREADS) {
-    a[0].merge(partials[4 * p + 0], partials[4 * p + 1]);
-    a[1].merge(partials[4 * p + 2], partials[4 * p + 3]);
+  // Thread t merges partials t, t + 256, t + 512, ... in that order; the loads
+  // of eight of them are issued before the first merge (the step kernel leaves
+  // one partial per tile, tens of thousands of them).
+  constexpr int U = 8;
+  for (int p0 = threadIdx.x; p0 < nparts; p0 += U * RED_THREADS) {
+    double v[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int p = p0 + u * RED_THREADS;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[u][k] = p < nparts ? partials[4 * p + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (p0 + u * RED_THREADS >= nparts) break;
+      a[0].merge(v[u][0], v[u][1]);
+      a[1].merge(v[u][2], v[u][3]);
+    }
   }
   block_merge<2>(a);
   if (threadIdx.x == 0) {

@@ -44,6 +44,25 @@ def test_relaxation_matches_oracle(bc, path):
     assert math.isclose(t_end, t_ref, rel_tol=1e-13), (t_end, t_ref)
 
 
+@pytest.mark.parametrize("ty", [8, 16])
+def test_relaxation_step_kernel_tile_shapes(ty):
+    """On the step kernel the first Newton iteration's sums come from the
+    kernel's own tiles (4 doubles per tile): both tile shapes, grids with
+    ragged tails in both directions."""
+    for nx, ny in ((61, 33), (203, 150)):
+        g, q0, b = wavy(REF, nx, ny, seed=nx)
+        dt = oracle.cfl_dt(g, q0, 0.5)
+        ref, t_ref, _ = oracle.rk4_relax(g, q0, b, dt, 9)
+        s = solver(g)
+        s.set_tile_y(ty)
+        s.set_bathymetry(dev(b))
+        qd = dev(q0)
+        t_end = s.step_relaxation(qd, dt, 9)
+        err = field_rel_err(host(qd), ref, STATE_FLOORS)
+        assert np.all(err <= 1e-12), (nx, ny, err)
+        assert math.isclose(t_end, t_ref, rel_tol=1e-13), (t_end, t_ref)
+
+
 def test_relaxation_single_step_parameter():
     g, q0, b = wavy(PER, 64, 64, seed=3)
     dt = oracle.cfl_dt(g, q0, 0.5)
