@@ -251,12 +251,21 @@ def run_adjoint(n, steps, label):
     w = min(20, steps)
     s.gauge_loss_grad(z0, w, dt, nodes, target[:w].contiguous())  # warm-up of the adjoint buffers
     t_grad, (L, gz, gb) = timed(lambda: s.gauge_loss_grad(z0, steps, dt, nodes, target))
+    # context: the same forward on the four-stage path (84 values per node and step)
+    s.set_step_path("stages")
+    qs = q.clone()
+    s.init_aux(qs)
+    s.step(qs, dt, 8)
+    t_fwd4, _ = timed(lambda: s.step(qs, dt, steps))
+    s.set_step_path("fused")
     res = {"grid": [g.nx, g.ny], "steps": steps, "gauges": int(len(gp.gauges)), "dt": dt,
            "checkpoint_every": int(np.ceil(np.sqrt(steps))), "loss": L,
            "forward_s": t_fwd, "forward_with_gauges_s": t_series, "gradient_s": t_grad,
            "adjoint_to_forward": t_grad / t_fwd,
+           "forward_four_stage_s": t_fwd4, "adjoint_to_four_stage_forward": t_grad / t_fwd4,
            "grad_norms": {"zeta0": float(torch.linalg.norm(gz)), "b": float(torch.linalg.norm(gb))}}
-    log(f"[{label}] forward {t_fwd:.3f} s, gradient {t_grad:.3f} s, adjoint:forward = {t_grad / t_fwd:.2f}")
+    log(f"[{label}] forward {t_fwd:.3f} s, gradient {t_grad:.3f} s, adjoint:forward = {t_grad / t_fwd:.2f} "
+        f"(four-stage forward {t_fwd4:.3f} s: {t_grad / t_fwd4:.2f})")
     s.close()
     torch.cuda.empty_cache()
     return res

@@ -231,9 +231,10 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, 
  * Every instance has its own sgn_params (grid size, domain, boundary types, g,
  * lambda; all instances share one dtype; no source terms) and its own time
  * step.  The tiles of all instances form one work list; each RK4 step is one
- * launch of a persistent kernel running the step tile of SGN_PATH_FUSED over
- * the whole list (default), or two launches running the stage-pair tiles of
- * SGN_PATH_PAIRS; the boundary variant is chosen per instance.  Steps are
+ * launch running the step tile of SGN_PATH_FUSED over the whole list
+ * (default), or two launches running the stage-pair tiles of SGN_PATH_PAIRS;
+ * the boundary variant is chosen per instance.  A launch has one workgroup
+ * per tile (default) or a persistent grid (sgn_batch_set_tiling).  Steps are
  * replayed from a captured HIP graph.  Results are identical, bit for bit, to
  * advancing each instance alone with sgn_step (every step path forms the same
  * values).
@@ -265,7 +266,8 @@ sgn_status sgn_batch_cfl_dt(sgn_batch* batch, double cfl, double* dt);
 sgn_status sgn_batch_set_step_path(sgn_batch* batch, int32_t path);
 /* Tile height (8 or 16; on the fused path 8 selects 64 x 8 tiles and 16
  * selects 32 x 16) and persistent workgroups per compute unit (1..16), or 0
- * for one workgroup per tile (no persistent loop; fewer registers). */
+ * for one workgroup per tile (the default: no persistent loop, fewer
+ * registers). */
 sgn_status sgn_batch_set_tiling(sgn_batch* batch, int32_t tile_y, int32_t blocks_per_cu);
 /* Time every (tile height 8 or 16, 0..6 workgroups per CU) candidate of the
  * current step path on one step from the

@@ -48,7 +48,7 @@ struct sgn_batch {
   bool desc_dirty = true;
   int path = SGN_PATH_FUSED;
   int tile_y = 16;  // tile height; the step tile holds 512 nodes (8: 64 x 8, 16: 32 x 16), pair tiles are 64 wide
-  int blocks_per_cu = 2;
+  int blocks_per_cu = 0;  // one workgroup per tile
   int num_cus = 256;
   hipGraphExec_t gexec = nullptr;
   int g_key = 0, g_bpc = 0;

@@ -1,17 +1,14 @@
-// sgn_batch.hpp -- an ensemble of independent problems in one persistent launch
-// per stage pair.
+// sgn_batch.hpp -- an ensemble of independent problems in one launch per RK4
+// step (step tiles) or per stage pair (pair tiles).
 //
 // Every instance has its own grid size, boundary types, spacing, g, lambda and
 // time step.  The tiles of all instances form one work list (instance-major,
-// row-major tiles within an instance).  A persistent grid of workgroups walks
-// the list: the list is cut into eight contiguous ranges, one per XCD, so tiles
-// of the same instance (and their shared halo rows) stay in one L2.  Each work
-// item runs the same pair_tile code as the single-problem kernel, with the
-// boundary variant chosen per instance at run time (uniform per workgroup).
-//
-// With the step kernel (the default), one launch per RK4 step runs the fused
-// step tile on every work item instead.  Either kernel also runs with one
-// workgroup per work item instead of a persistent grid.
+// row-major tiles within an instance), cut into eight contiguous ranges, one per
+// XCD, so tiles of the same instance (and their shared halo rows) stay in one
+// L2.  Each work item runs the same tile code as the single-problem kernels,
+// with the boundary variant chosen per instance at run time (uniform per
+// workgroup).  A launch has either one workgroup per work item or a persistent
+// grid of workgroups that walks the list.
 #pragma once
 
 #include "sgn_fused.hpp"
