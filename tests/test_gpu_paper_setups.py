@@ -4,7 +4,10 @@ oracle by exact windows (see gpu_util.check_windows) and by conservation:
 * solitary wave over a Gaussian obstacle (periodic, anisotropic grid) at the
   smallest and the paper's own resolution of its scaling study;
 * the long-term cylindrical dam break at its full size, 10000 x 10000 nodes
-  (10^8; 4 GB per FP64 state), reflecting walls.
+  (10^8; 4 GB per FP64 state), reflecting walls;
+* the Riemann problem at the paper's size ([-600, 600], dx = 0.3, to
+  t = 47.434): the mean state and the leading soliton's height against the
+  values the paper prints (tests/golden/riemann_problem.txt).
 """
 
 import numpy as np
@@ -64,3 +67,29 @@ def test_cylindrical_dam_break_full_size():
     check_windows(g, q0, p.b, got, dt, STEPS, windows)
     assert abs(m1 - m0) <= 1e-13 * abs(m0)
     assert abs(e1 - e0) <= 1e-9 * abs(e0)
+
+
+def test_riemann_problem_matches_the_paper():
+    from golden_values import load
+    from riemann_check import check_riemann
+
+    G = load("riemann_problem")
+    n = int(round((G["x_max"] - G["x_min"]) / G["dx"])) + 1
+    g = W.Grid(n, 4, G["x_min"], G["x_max"], 0.0, 1.0, W.REFLECTING, W.PERIODIC, 9.81, G["lambda"])
+    x = g.x_nodes()
+    q = np.zeros((5,) + g.shape)
+    q[0] = (G["h_R"] + 0.5 * (G["h_L"] - G["h_R"]) * (1.0 - np.tanh(0.5 * x)))[None, :]
+    s = solver(g)
+    s.set_bathymetry(dev(np.zeros(g.shape)))
+    qd = dev(q)
+    s.init_aux(qd)
+    T = G["t_end"]
+    ns = int(np.ceil(T / oracle.cfl_dt(g, host(qd), 0.5)))
+    m0, _ = s.mass_energy(qd)
+    s.step(qd, T / ns, ns)
+    s.check()
+    m1, _ = s.mass_energy(qd)
+    got = host(qd)
+    assert abs(m1 - m0) <= 1e-13 * abs(m0)
+    plateau, hm = check_riemann(x, got[0][0], G)
+    print(f"\nRiemann problem, {n} x 4 nodes, {ns} steps: h* = {plateau:.4f}, h_max = {hm:.4f}")
