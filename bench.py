@@ -57,10 +57,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
 # they had when the counters were taken.
-STEP_TRAFFIC_BYTES_PER_NODE = (1185238843.0 + 671088640.0) / 16777216
+STEP_TRAFFIC_BYTES_PER_NODE = (1185467396.8 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "cb9ff63bf6ccf84d351e4bc4a829708ecd01861d4ad92f94fa4b58032f140a06"
+STEP_SOURCES_SHA256 = "6dcefb76e68d75b7a196eec1acdabedae127f912fea6bcf5f370b58fee613f40"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
