@@ -392,8 +392,9 @@ def torch_f64():
     return torch.float64
 
 
-def cpu_baseline(problem, steps=1):
-    """The FP64 oracle (single thread, as written) on the same workload."""
+def cpu_baseline(problem, steps=2):
+    """The FP64 oracle (single thread, as written) on the same workload: two RK4
+    steps, about 20 s of host time."""
     import numpy as np
     import oracle
     oracle.build() if not os.path.exists(oracle._LIB) else None
@@ -531,8 +532,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on one step of the same workload")
-        cpu = cpu_baseline(prob, 1)
+        log("[bench] timing the CPU oracle on two steps of the same workload")
+        cpu = cpu_baseline(prob)
         log(f"[bench] cpu {cpu['value']:.3e} cell-stage/s")
 
     cells = n * n
