@@ -60,7 +60,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 STEP_TRAFFIC_BYTES_PER_NODE = (1185467396.8 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "6dcefb76e68d75b7a196eec1acdabedae127f912fea6bcf5f370b58fee613f40"
+STEP_SOURCES_SHA256 = "59c870d162a87e74409964bb8f56973fa6782ff46a1d4e84753bb66b8daeb43d"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

@@ -17,10 +17,10 @@
 //
 // Thread map: thread t owns the two tile nodes (t mod TX, 2 floor(t / TX) + k),
 // k = 0, 1, in every stage, so their q and acc stay in registers; the pair
-// shares two of its y-neighbours.  Ring nodes are
-// numbered by distance (all of ring 1 first, then ring 2, then ring 3); thread
-// t evaluates ring nodes t and t + 256 in every stage whose region contains
-// them, so the q of a ring node is read from LDS once, in the first stage.
+// shares two of its y-neighbours.  Ring nodes are numbered by distance (all of
+// ring 1 first, then ring 2, then ring 3); thread t evaluates ring nodes t and
+// t + 256 in every stage whose region contains them, so the q of a ring node is
+// read from LDS once, in the first stage.
 //
 // The output buffer must not alias the input (neighbouring tiles read the
 // halo of q); sgn_step alternates between the caller's buffer and the
@@ -40,13 +40,13 @@ struct StepGeom {
   static constexpr int TY = STEP_NODES / TX;
   static constexpr int RX = TX + 2 * STEP_HALO;
   static constexpr int RY = TY + 2 * STEP_HALO;
-  static constexpr int ROWS = STAGE_THREADS / TX;  // tile rows covered by one pass of the threads
   // nodes of the ring at distance d around the tile
   static constexpr int ring(int d) { return 2 * (TX + 2 * d) + 2 * (TY + 2 * d - 2); }
   static constexpr int RING1 = ring(1);
   static constexpr int RING2 = RING1 + ring(2);
   static constexpr int RING3 = RING2 + ring(3);
   static_assert(STEP_NODES % TX == 0 && STAGE_THREADS % TX == 0, "tile width must divide 256");
+  static_assert(2 * STAGE_THREADS / TX == TY, "each thread owns two vertically adjacent nodes");
   static_assert(RING3 <= 2 * STAGE_THREADS, "two ring slots per thread");
 };
 
