@@ -47,3 +47,17 @@ def test_binding_refuses_without_gpu():
     from paper_2601_02540_amd import workloads as W
     with pytest.raises(RuntimeError):
         binding.Solver(W.Grid(8, 8, 0.0, 1.0, 0.0, 1.0))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before
+    touching a device."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["requested_gpus"] == 2 and "one GPU" in msg["error"]
