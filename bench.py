@@ -60,11 +60,11 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 STEP_TRAFFIC_BYTES_PER_NODE = (1185467396.8 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "59c870d162a87e74409964bb8f56973fa6782ff46a1d4e84753bb66b8daeb43d"
+STEP_SOURCES_SHA256 = "d5c92e708acaeb45905f95324740bf8e7451ae18ca64b9f73258041a8bba63b0"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
-ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation"}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation", "totals"}
 
 
 def log(msg):
@@ -387,6 +387,49 @@ def run_relaxation(problem, steps, warmup, path, tile_y):
     return res
 
 
+def run_totals(problem, steps, warmup, tile_y):
+    """RK4 steps with mass and energy recorded after every step (the step
+    kernel's totals epilogue), against the plain step and against a separate
+    totals pass after every step, on the main workload."""
+    import torch
+    from paper_2601_02540_amd.binding import Solver
+    grid = problem.grid
+    s = Solver(grid, torch.float64)
+    if tile_y is not None:
+        s.set_tile_y(tile_y)
+    b = torch.from_numpy(problem.b).cuda()
+    q = torch.from_numpy(problem.q0).cuda()
+    s.set_bathymetry(b)
+    s.init_aux(q)
+    dt = s.cfl_dt(q, 0.5)
+    _, e0 = s.mass_energy(q)
+    s.step_totals(q, dt, warmup)
+    s.step(q, dt, warmup)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record(s.stream)
+    series = s.step_totals(q, dt, steps)
+    ev[1].record(s.stream)
+    s.step(q, dt, steps)
+    ev[2].record(s.stream)
+    ev[2].synchronize()
+    t_series = ev[0].elapsed_time(ev[1]) / steps
+    t_plain = ev[1].elapsed_time(ev[2]) / steps
+    # a separate totals call (one pass over the state, synchronizing)
+    n_sep = 20
+    t0 = time.perf_counter()
+    for _ in range(n_sep):
+        s.mass_energy(q)
+    t_call = (time.perf_counter() - t0) / n_sep * 1e3
+    e = series[:, 1].cpu()
+    res = {"ms_per_step_recorded": t_series, "ms_per_step_plain": t_plain, "ms_totals_call": t_call,
+           "energy_drift_rel_over_series": float((e[-1] - e[0]) / abs(e0)), "steps": steps}
+    log(f"[totals] {t_series:.3f} ms/step with mass and energy recorded every step (plain step {t_plain:.3f}, "
+        f"plus a separate totals call {t_call:.3f})")
+    s.close()
+    return res
+
+
 def torch_f64():
     import torch
     return torch.float64
@@ -463,7 +506,8 @@ def main():
     ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
-                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation "
+                    help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation,"
+                         "totals "
                          "(default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -520,6 +564,8 @@ def main():
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
     if "relaxation" in chosen:
         variants["relaxation_f64"] = run_relaxation(prob, min(args.steps, 200), 8, P, T)
+    if "totals" in chosen:
+        variants["recorded_totals_f64"] = run_totals(prob, min(args.steps, 200), 8, T)
     if "paper" in chosen:
         variants["paper_setups"] = run_paper_setups(P, T)
     if args.long_dam_break:

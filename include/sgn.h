@@ -153,6 +153,19 @@ sgn_status sgn_step(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0)
  * source term (SGN_E_UNSUPPORTED). */
 sgn_status sgn_step_relaxation(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0, double* t_end);
 
+/* Classical RK4 like sgn_step, recording the totals of every step: after
+ * step k (1-based), series[2 (k-1)] = mass and series[2 (k-1) + 1] = energy of
+ * the state (the definitions of sgn_mass_energy).  The steps run on the step
+ * kernel whatever the step path (every path forms the same states), which
+ * reduces the totals of each tile from the values it writes, so the series
+ * costs no pass over the state (totals summed in FP64, compensated,
+ * deterministic; they agree with sgn_mass_energy to rounding).  series: device
+ * memory, 2 nsteps doubles, FP64 whatever the dtype; not NULL unless nsteps is
+ * 0 (a no-op).  Steps are
+ * replayed from a captured graph; asynchronous.  Requires no source term
+ * (SGN_E_UNSUPPORTED). */
+sgn_status sgn_step_totals(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* series);
+
 /* Total mass 1^T M h (FP64 result, compensated deterministic summation). */
 sgn_status sgn_mass(sgn_ctx* ctx, const void* q, double* out);
 

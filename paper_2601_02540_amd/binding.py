@@ -92,6 +92,7 @@ def load_library() -> ctypes.CDLL:
         "sgn_batch_cfl_dt": ([vp, d, dp], st),
         "sgn_batch_set_tiling": ([vp, ctypes.c_int32, ctypes.c_int32], st),
         "sgn_step_relaxation": ([vp, vp, d, ctypes.c_int64, d, dp], st),
+        "sgn_step_totals": ([vp, vp, d, ctypes.c_int64, vp], st),
         "sgn_batch_set_step_path": ([vp, ctypes.c_int32], st),
         "sgn_batch_autotune": ([vp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), dp], st),
         "sgn_batch_check": ([vp, ctypes.POINTER(ctypes.c_int32)], st),
@@ -223,6 +224,15 @@ class Solver:
         self._chk(self.lib.sgn_step_relaxation(self.ctx, self._state(q), float(dt), int(nsteps), float(t0),
                                                ctypes.byref(t_end)))
         return t_end.value
+
+    def step_totals(self, q, dt: float, nsteps: int = 1):
+        """RK4 steps in place, recording mass and energy after every step;
+        returns a (nsteps, 2) FP64 tensor on the device (asynchronous)."""
+        torch = _torch()
+        series = torch.empty((max(int(nsteps), 0), 2), dtype=torch.float64, device=self.device)
+        self._chk(self.lib.sgn_step_totals(self.ctx, self._state(q), float(dt), int(nsteps),
+                                           ctypes.c_void_p(series.data_ptr())))
+        return series
 
     def mass_energy(self, q) -> Tuple[float, float]:
         m, e = ctypes.c_double(), ctypes.c_double()

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgn.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("sgn_lib.hip", "sgn_batch.hip", "sgn_adjoint.hip", "sgn_relax.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("sgn_lib.hip", "sgn_batch.hip", "sgn_adjoint.hip", "sgn_relax.hip",
+                                                "sgn_totals.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hpp", ".h"))] + [
     os.path.join(INCLUDE, "sgn.h")]
 

@@ -33,6 +33,7 @@
 namespace sgn {
 
 constexpr int STEP_NODES = 512;  // owned nodes per tile (two per thread)
+
 constexpr int STEP_HALO = 4;     // one node per right-hand side of the step
 
 template <int TX>
@@ -105,11 +106,11 @@ __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
 // One tile (origin i0, j0) of one RK4 step, executed by a whole workgroup.
 // SAVE (the adjoint's recomputation): also write the intermediate stages
 // Y2, Y3, Y4 of the owned nodes to ysave, three consecutive states.
-// RELAX (relaxation RK4): also reduce the tile's sums of M s(1) and M s'(1)
-// (relax_node_terms at gam = 1, from the step's input and output values held
-// in registers) into rpart[0..3] (compensated: sum, error, sum, error).
+// EPI (EPI_RELAX or EPI_TOTALS): also reduce the tile's two sums (see the
+// enum; from the step's input and output values held in registers) into
+// rpart[0..3].
 // The caller synchronizes the workgroup before reusing `s` for another tile.
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, bool RELAX = false>
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, int EPI = EPI_NONE>
 __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridConst& gc, int i0, int j0,
                                           const T* __restrict__ q, const T* __restrict__ bplane,
                                           T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
@@ -185,7 +186,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   T qo[2][5], acc[2][5], qr[2][5];
   int health = 0;
   CSum rsum[2];
-  if (RELAX) {
+  if (EPI != EPI_NONE) {
     rsum[0].init();
     rsum[1].init();
   }
@@ -234,7 +235,14 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
         if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
         const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
         if (!isfinite(sum)) health |= FLAG_NONFINITE;
-        if (RELAX) {
+        if (EPI == EPI_TOTALS) {
+          const double M = axis_weight(i, nx, gc.bc_x, gc.dx) * axis_weight(j, ny, gc.bc_y, gc.dy);
+          const double bb = (double)s.f[5][ly0 + k + STEP_HALO][lx + STEP_HALO];
+          rsum[0].add(M * (double)nv[0]);
+          rsum[1].add(M * energy_density((double)nv[0], (double)nv[1], (double)nv[2], (double)nv[3], (double)nv[4],
+                                         bb, gc.g, gc.lam));
+        }
+        if (EPI == EPI_RELAX) {
           double x[5], d[5];
 #pragma unroll
           for (int f = 0; f < 5; ++f) {
@@ -324,7 +332,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     __syncthreads();
   }
   if (health) atomicOr(flag, health);
-  if (RELAX) {
+  if (EPI != EPI_NONE) {
     block_merge<2>(rsum);
     if (tid == 0) {
       rpart[0] = rsum[0].s;
@@ -335,8 +343,8 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   }
 }
 
-// RELAX: rpart holds 4 doubles per tile, in tile order.
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false, bool RELAX = false>
+// EPI != EPI_NONE: rpart holds 4 doubles per tile, in tile order.
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false, int EPI = EPI_NONE>
 __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
                                                              const T* __restrict__ bplane, T* __restrict__ qout,
                                                              T c6, T c3, T c2, T c1, double t0, double dt,
@@ -347,9 +355,9 @@ __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc,
   const int ntx = (gc.nx + TX - 1) / TX;
   const int nty = (gc.ny + TY - 1) / TY;
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  step_tile<T, BCX, BCY, SRC, TX, SAVE, SRC ? 0 : 1, RELAX>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane,
-                                                            qout, c6, c3, c2, c1, t0, dt, flag, ysave,
-                                                            RELAX ? rpart + 4 * tile : nullptr);
+  step_tile<T, BCX, BCY, SRC, TX, SAVE, SRC ? 0 : 1, EPI>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane,
+                                                          qout, c6, c3, c2, c1, t0, dt, flag, ysave,
+                                                          EPI != EPI_NONE ? rpart + 4 * tile : nullptr);
 }
 
 }  // namespace sgn

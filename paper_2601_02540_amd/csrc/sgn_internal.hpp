@@ -51,8 +51,9 @@ struct sgn_ctx {
   void* ya = nullptr;
   void* yb = nullptr;
   double* partials = nullptr;
-  double* relax_partials = nullptr;  // 4 doubles per step tile (relaxation on the step kernel)
-  size_t relax_partials_cap = 0;     // doubles allocated there
+  double* tile_partials = nullptr;  // 4 doubles per step tile (the step kernel's epilogue sums)
+  size_t tile_partials_cap = 0;     // doubles allocated there
+  int* series_counter = nullptr;    // next slot of a recorded totals series (sgn_step_totals)
   double* result = nullptr;
   double* host_result = nullptr;
   int* flag = nullptr;
@@ -62,7 +63,9 @@ struct sgn_ctx {
   int tile_y = 8;     // stage and pair kernels
   int step_tile = 16;  // step kernel: 16 selects 32 x 16, 8 selects 64 x 8
   sgn_host::GraphCache graphs[2];
-  sgn_host::GraphCache relax_graph;  // relaxation steps (sgn_step_relaxation)
+  sgn_host::GraphCache relax_graph;   // relaxation steps (sgn_step_relaxation)
+  sgn_host::GraphCache totals_graph;  // steps with recorded totals (sgn_step_totals)
+  double* totals_series = nullptr;    // the series pointer captured in totals_graph
   sgn_host::AdjointBuffers adj;
   std::string err;
 };
@@ -81,13 +84,17 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t);
 // One RK4 step by the step kernel from `cur` into `oth` (distinct buffers);
 // with `ysave` non-null the stage states Y2, Y3, Y4 go to three consecutive
-// state slots there; with `rpart` non-null each tile's relaxation sums at
-// gam = 1 go to rpart[4 tile ..] (step_tiles(c) tiles).  Neither with source
-// terms, and not both.
+// state slots there; with `rpart` non-null each tile's epilogue sums `epi`
+// (sgn::EPI_RELAX: relaxation sums at gam = 1; sgn::EPI_TOTALS: mass and
+// energy of the new state) go to rpart[4 tile ..] (step_tiles(c) tiles).
+// Neither with source terms, and not both.
 hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
-                             void* ysave, double* rpart = nullptr);
+                             void* ysave, double* rpart = nullptr, int epi = 0);
 // Number of tiles of the step kernel in the current tile shape.
 int step_tiles(const sgn_ctx* c);
+// Makes c->tile_partials hold the epilogue sums of either tile shape
+// (synchronizes and drops the graphs that captured an older buffer).
+sgn_status ensure_tile_partials(sgn_ctx* c);
 
 }  // namespace sgn_host
 

@@ -1,6 +1,7 @@
 // sgn_lib.hip -- C ABI of include/sgn.h: context, validation, launches, graphs.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -58,6 +59,9 @@ void destroy_graphs(sgn_ctx* c) {
   }
   if (c->relax_graph.exec) (void)hipGraphExecDestroy(c->relax_graph.exec);
   c->relax_graph = GraphCache{};
+  if (c->totals_graph.exec) (void)hipGraphExecDestroy(c->totals_graph.exec);
+  c->totals_graph = GraphCache{};
+  c->totals_series = nullptr;
 }
 
 int reduce_blocks(const sgn_ctx* c) { return c->p.ny < sgn::RED_MAX_BLOCKS ? c->p.ny : sgn::RED_MAX_BLOCKS; }
@@ -151,7 +155,7 @@ hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const v
 
 template <typename T, int TX>
 hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
-                           void* ysave, double* rpart) {
+                           void* ysave, double* rpart, int epi) {
   constexpr int TY = sgn::STEP_NODES / TX;
   const int ntx = (c->p.nx + TX - 1) / TX;
   const int nty = (c->p.ny + TY - 1) / TY;
@@ -164,18 +168,23 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 #define SGN_LAUNCH_K(BX, BY, S, SV, RX)                                                                         \
   hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,       \
                      (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys, rpart)
-#define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false, false)
+#define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false, sgn::EPI_NONE)
   const int bx = c->p.bc_x, by = c->p.bc_y;
-  if (rpart) {  // relaxation partial sums (no source terms, no stage saving)
-    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, false, true);
-    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, false, true);
-    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, false, true);
-    else SGN_LAUNCH_K(1, 1, false, false, true);
+  if (rpart && epi == sgn::EPI_RELAX) {  // relaxation sums (no source terms, no stage saving)
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, false, sgn::EPI_RELAX);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, false, sgn::EPI_RELAX);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, false, sgn::EPI_RELAX);
+    else SGN_LAUNCH_K(1, 1, false, false, sgn::EPI_RELAX);
+  } else if (rpart) {  // mass and energy of the new state (no source terms, no stage saving)
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, false, sgn::EPI_TOTALS);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, false, sgn::EPI_TOTALS);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, false, sgn::EPI_TOTALS);
+    else SGN_LAUNCH_K(1, 1, false, false, sgn::EPI_TOTALS);
   } else if (ys) {  // stage saving (no source terms)
-    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true, false);
-    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true, false);
-    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true, false);
-    else SGN_LAUNCH_K(1, 1, false, true, false);
+    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true, sgn::EPI_NONE);
+    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true, sgn::EPI_NONE);
+    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true, sgn::EPI_NONE);
+    else SGN_LAUNCH_K(1, 1, false, true, sgn::EPI_NONE);
   } else if (!src) {
     if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
     else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
@@ -194,15 +203,15 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 
 // One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct);
 // with `ysave`, also the stage states Y2, Y3, Y4 (three consecutive states);
-// with `rpart`, also the relaxation sums of every tile.
+// with `rpart`, also the epilogue sums `epi` (sgn::EPI_*) of every tile.
 hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
-                        void* ysave = nullptr, double* rpart = nullptr) {
+                        void* ysave = nullptr, double* rpart = nullptr, int epi = sgn::EPI_NONE) {
   if (c->p.dtype == SGN_F64) {
-    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave, rpart);
-    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave, rpart);
+    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
   }
-  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave, rpart);
-  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave, rpart);
+  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
 }
 
 // Two RK4 steps on the fused path: q -> acc -> q.
@@ -333,14 +342,30 @@ hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const vo
 }
 
 hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, void* oth, double dt, double t,
-                             void* ysave, double* rpart) {
-  return ::launch_fused(c, s, cur, oth, dt, t, ysave, rpart);
+                             void* ysave, double* rpart, int epi) {
+  return ::launch_fused(c, s, cur, oth, dt, t, ysave, rpart, epi);
 }
 
 int step_tiles(const sgn_ctx* c) {
   const int tx = c->step_tile == 16 ? 32 : 64;
   const int ty = sgn::STEP_NODES / tx;
   return ((c->p.nx + tx - 1) / tx) * ((c->p.ny + ty - 1) / ty);
+}
+
+sgn_status ensure_tile_partials(sgn_ctx* c) {
+  // room for the larger tile count of the two tile shapes
+  const size_t nx = (size_t)c->p.nx, ny = (size_t)c->p.ny;
+  const size_t tiles = std::max(((nx + 31) / 32) * ((ny + 15) / 16), ((nx + 63) / 64) * ((ny + 7) / 8));
+  if (c->tile_partials_cap >= 4 * tiles) return SGN_OK;
+  SGN_HIPCHK(c, hipStreamSynchronize(c->stream));  // earlier steps may still write the old buffer
+  if (c->tile_partials) (void)hipFree(c->tile_partials);
+  c->tile_partials = nullptr;
+  c->tile_partials_cap = 0;
+  destroy_graphs(c);  // captured graphs hold the old address
+  if (hipMalloc((void**)&c->tile_partials, 4 * tiles * sizeof(double)) != hipSuccess)
+    return fail(c, SGN_E_ALLOC, "per-tile partial sums");
+  c->tile_partials_cap = 4 * tiles;
+  return SGN_OK;
 }
 
 hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, double dt, double t) {
@@ -467,7 +492,8 @@ sgn_status sgn_destroy(sgn_ctx* c) {
   if (c->ya) (void)hipFree(c->ya);
   if (c->yb) (void)hipFree(c->yb);
   if (c->partials) (void)hipFree(c->partials);
-  if (c->relax_partials) (void)hipFree(c->relax_partials);
+  if (c->tile_partials) (void)hipFree(c->tile_partials);
+  if (c->series_counter) (void)hipFree(c->series_counter);
   if (c->result) (void)hipFree(c->result);
   if (c->flag) (void)hipFree(c->flag);
   if (c->host_result) (void)hipHostFree(c->host_result);

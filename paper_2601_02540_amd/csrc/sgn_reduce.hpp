@@ -17,6 +17,23 @@ namespace sgn {
 constexpr int RED_THREADS = 256;
 constexpr int RED_MAX_BLOCKS = 1024;
 
+// Optional epilogue of the step tile: two compensated sums over the tile's
+// owned nodes, written as 4 doubles per tile (sum, error, sum, error).
+enum : int {
+  EPI_NONE = 0,
+  EPI_RELAX = 1,   // M s(1) and M s'(1) of relaxation RK4 (relax_node_terms at gam = 1)
+  EPI_TOTALS = 2,  // M h and M E of the new state (mass and energy)
+};
+
+// Energy density h (u^2 + v^2)/2 + h w^2/6 + g h (h + 2b)/2 + lam h (eta/h - 1)^2/6
+// of one node (Theorem 2's E, whose M-weighted sum is the total energy).
+__device__ __forceinline__ double energy_density(double h, double u, double v, double w, double eta, double b,
+                                                 double g, double lam) {
+  const double rm1 = eta * (1.0 / h) - 1.0;
+  const double e = w * w * (1.0 / 6.0) + 0.5 * g * (h + 2.0 * b) + lam * (1.0 / 6.0) * rm1 * rm1;
+  return h * (0.5 * (u * u + v * v) + e);
+}
+
 // Relaxation RK4: one node's s(gam) = (e(q + gam d) - e(q)) / gam of the energy
 // density e and its derivative s'(gam), from the node's values x, increments d
 // and bottom b.  Each part of e is written out as a polynomial in gam (rational
@@ -96,14 +113,11 @@ __global__ __launch_bounds__(RED_THREADS) void totals_partial(const GridConst gc
       const size_t o = (size_t)j * nx + i;
       const double h = (double)q[o], u = (double)q[N + o], v = (double)q[2 * N + o];
       const double w = (double)q[3 * N + o], eta = (double)q[4 * N + o], b = (double)bplane[o];
-      const double ih = 1.0 / h;
       if (WHAT == 0) {
-        const double rm1 = eta * ih - 1.0;
-        const double e = w * w * (1.0 / 6.0) + 0.5 * g * (h + 2.0 * b) + lam * (1.0 / 6.0) * rm1 * rm1;
         a[0].add(M * h);
-        a[1].add(M * (h * (0.5 * (u * u + v * v) + e)));
+        a[1].add(M * energy_density(h, u, v, w, eta, b, g, lam));
       } else {
-        const double r = eta * ih;
+        const double r = eta * (1.0 / h);
         const double dEh = 0.5 * u * u + 0.5 * v * v + w * w * (1.0 / 6.0) + g * h + g * b +
                            lam * (1.0 / 6.0) * (1.0 - r * r);
         const double ht = (double)dq[o];
@@ -122,6 +136,54 @@ __global__ __launch_bounds__(RED_THREADS) void totals_partial(const GridConst gc
     partials[4 * blockIdx.x + 2] = a[1].s;
     partials[4 * blockIdx.x + 3] = a[1].c;
   }
+}
+
+// Per-tile partials (4 doubles each: two compensated sums) of the step kernel's
+// epilogue, reduced in two deterministic levels.  Level 1: block b merges
+// partials [b per, min((b + 1) per, n)), thread t those at b per + t + 256 m.
+static __global__ __launch_bounds__(RED_THREADS) void partials_merge(const double* __restrict__ in, int n, int per,
+                                                              double* __restrict__ out) {
+  CSum a[2];
+  a[0].init();
+  a[1].init();
+  const int lo = blockIdx.x * per;
+  const int hi = lo + per < n ? lo + per : n;
+  for (int p = lo + threadIdx.x; p < hi; p += RED_THREADS) {
+    a[0].merge(in[4 * p + 0], in[4 * p + 1]);
+    a[1].merge(in[4 * p + 2], in[4 * p + 3]);
+  }
+  block_merge<2>(a);
+  if (threadIdx.x == 0) {
+    out[4 * blockIdx.x + 0] = a[0].s;
+    out[4 * blockIdx.x + 1] = a[0].c;
+    out[4 * blockIdx.x + 2] = a[1].s;
+    out[4 * blockIdx.x + 3] = a[1].c;
+  }
+}
+
+// Level 2 (one block): the two totals of the n level-1 partials go to
+// series[2 k] and series[2 k + 1], k = *counter, and the counter advances.
+static __global__ __launch_bounds__(RED_THREADS) void series_final(const double* __restrict__ in, int n,
+                                                            double* __restrict__ series, int* __restrict__ counter) {
+  CSum a[2];
+  a[0].init();
+  a[1].init();
+  for (int p = threadIdx.x; p < n; p += RED_THREADS) {
+    a[0].merge(in[4 * p + 0], in[4 * p + 1]);
+    a[1].merge(in[4 * p + 2], in[4 * p + 3]);
+  }
+  block_merge<2>(a);
+  if (threadIdx.x == 0) {
+    const int k = *counter;
+    series[2 * k] = a[0].s + a[0].c;
+    series[2 * k + 1] = a[1].s + a[1].c;
+    *counter = k + 1;
+  }
+}
+
+// *counter = 0 (start of a recorded series).
+static __global__ void counter_reset(int* __restrict__ counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
 // One block: combines nparts partials in block order; result[0..1] = totals.

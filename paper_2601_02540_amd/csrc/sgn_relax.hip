@@ -31,14 +31,15 @@ hipError_t enqueue_relaxed_step_t(const sgn_ctx* c, hipStream_t s, void* q, doub
   // the step kernel, which also forms the sums of the first Newton iteration
   // (gam = 1) per tile from the values it holds, saving that pass over q, acc, b.
   const bool fused = c->step_path != SGN_PATH_PAIRS;
-  hipError_t e = fused ? sgn_host::enqueue_step_into(c, s, q, c->acc, dt, 0.0, nullptr, c->relax_partials)
+  hipError_t e = fused ? sgn_host::enqueue_step_into(c, s, q, c->acc, dt, 0.0, nullptr, c->tile_partials,
+                                                     sgn::EPI_RELAX)
                        : sgn_host::enqueue_pair_step(c, s, q, c->acc, dt, 0.0);
   if (e) return e;
   const int nb = reduce_blocks(c);
   double* rs = relax_scalars(c);
   for (int it = 0; it < 2; ++it) {
     if (it == 0 && fused) {
-      hipLaunchKernelGGL(sgn::relax_newton, dim3(1), dim3(sgn::RED_THREADS), 0, s, (const double*)c->relax_partials,
+      hipLaunchKernelGGL(sgn::relax_newton, dim3(1), dim3(sgn::RED_THREADS), 0, s, (const double*)c->tile_partials,
                          sgn_host::step_tiles(c), rs, 1, 0, dt);
       continue;
     }
@@ -73,23 +74,7 @@ sgn_status sgn_step_relaxation(sgn_ctx* c, void* q, double dt, int64_t nsteps, d
   if (!std::isfinite(t0)) return fail(c, SGN_E_ARG, "t0 must be finite");
   if (c->p.source != SGN_SRC_NONE)
     return fail(c, SGN_E_UNSUPPORTED, "relaxation needs the energy-conserving semi-discretization (no source terms)");
-  // per-tile sums of the step kernel: room for the larger tile count of the two tile shapes
-  if (c->step_path != SGN_PATH_PAIRS) {
-    const size_t nx = (size_t)c->p.nx, ny = (size_t)c->p.ny;
-    const size_t tiles = std::max(((nx + 31) / 32) * ((ny + 15) / 16), ((nx + 63) / 64) * ((ny + 7) / 8));
-    if (c->relax_partials_cap < 4 * tiles) {
-      HIPCHK(c, hipStreamSynchronize(c->stream));  // an earlier relaxation may still read the old buffer
-      if (c->relax_partials) (void)hipFree(c->relax_partials);
-      c->relax_partials = nullptr;
-      c->relax_partials_cap = 0;
-      if (hipMalloc((void**)&c->relax_partials, 4 * tiles * sizeof(double)) != hipSuccess)
-        return fail(c, SGN_E_ALLOC, "relaxation partial sums");
-      c->relax_partials_cap = 4 * tiles;
-      auto& g = c->relax_graph;  // a captured graph holds the old address
-      if (g.exec) (void)hipGraphExecDestroy(g.exec);
-      g = sgn_host::GraphCache{};
-    }
-  }
+  if (c->step_path != SGN_PATH_PAIRS && (st = sgn_host::ensure_tile_partials(c))) return st;
   // the time accumulator starts at t0
   hipLaunchKernelGGL(sgn::relax_set_time, dim3(1), dim3(64), 0, c->stream, relax_scalars(c), t0);
   HIPCHK(c, hipGetLastError());
