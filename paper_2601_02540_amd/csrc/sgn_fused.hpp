@@ -153,7 +153,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
         const int cc = idx - rr * RX;
 #pragma unroll
         for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
-        s.f[6][rr][cc] = T(1) / v[it][0];
+        s.f[6][rr][cc] = recip_staged(v[it][0]);
       }
     }
   }
@@ -318,7 +318,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
       const int r = ly0 + k + STEP_HALO, c = lx + STEP_HALO;
 #pragma unroll
       for (int f = 0; f < 5; ++f) s.f[f][r][c] = ro[k][f];
-      s.f[6][r][c] = T(1) / ro[k][0];
+      s.f[6][r][c] = recip_staged(ro[k][0]);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -327,7 +327,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
       const int r = ring_r[k] + STEP_HALO, c = ring_c[k] + STEP_HALO;
 #pragma unroll
       for (int f = 0; f < 5; ++f) s.f[f][r][c] = rr[k][f];
-      s.f[6][r][c] = T(1) / rr[k][0];
+      s.f[6][r][c] = recip_staged(rr[k][0]);
     }
     __syncthreads();
   }

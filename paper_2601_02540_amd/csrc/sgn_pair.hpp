@@ -147,7 +147,7 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
     s.f[3][rr][cc] = Yin[3 * N + o];
     s.f[4][rr][cc] = Yin[4 * N + o];
     s.f[5][rr][cc] = bplane[o];
-    s.f[6][rr][cc] = T(1) / h;
+    s.f[6][rr][cc] = recip_staged(h);
   }
 
   // Own-node operands fetched before the barrier.
@@ -263,12 +263,12 @@ __device__ __forceinline__ void pair_tile(PairSmem<T, TY>& s, const GridConst& g
     }
 #pragma unroll
     for (int f = 0; f < 5; ++f) s.f[f][r][c] = mid[k][f];
-    s.f[6][r][c] = T(1) / mid[k][0];
+    s.f[6][r][c] = recip_staged(mid[k][0]);
   }
   if (ring_valid) {
 #pragma unroll
     for (int f = 0; f < 5; ++f) s.f[f][ring_r][ring_c] = ring_mid[f];
-    s.f[6][ring_r][ring_c] = T(1) / ring_mid[0];
+    s.f[6][ring_r][ring_c] = recip_staged(ring_mid[0]);
   }
   __syncthreads();
 

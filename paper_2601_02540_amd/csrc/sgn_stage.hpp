@@ -196,7 +196,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void stage_kernel(const GridConst gc
     s.f[3][rr][cc] = Y[3 * N + o];
     s.f[4][rr][cc] = Y[4 * N + o];
     s.f[5][rr][cc] = bplane[o];
-    s.f[6][rr][cc] = T(1) / h;
+    s.f[6][rr][cc] = recip_staged(h);
   }
 
   // Own-node operands of the stage update, fetched before the barrier so the

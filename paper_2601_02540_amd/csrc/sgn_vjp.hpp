@@ -387,7 +387,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, 
     s.f[3][rr][cc] = Y[3 * N + o];
     s.f[4][rr][cc] = Y[4 * N + o];
     s.f[5][rr][cc] = bplane[o];
-    s.f[6][rr][cc] = T(1) / h;
+    s.f[6][rr][cc] = recip_staged(h);
 #pragma unroll
     for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = a_in * Kin[f * N + o];
   }
