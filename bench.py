@@ -57,10 +57,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
 # they had when the counters were taken.
-STEP_TRAFFIC_BYTES_PER_NODE = (1185467396.8 + 671088640.0) / 16777216
+STEP_TRAFFIC_BYTES_PER_NODE = (1193634395.4 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "d5c92e708acaeb45905f95324740bf8e7451ae18ca64b9f73258041a8bba63b0"
+STEP_SOURCES_SHA256 = "5798bc0dcc42674757bd9f75d78e6060024a480582a2df549ff5f2ef4bc827f5"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
