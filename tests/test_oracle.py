@@ -11,7 +11,8 @@ Pin map (oracle function -> tests):
                                         test_mms_second_order, test_solitary_second_order
   SAT closed form                    -> test_sat_closed_form
   rhs_jvp (complex step)             -> test_jvp_against_finite_differences
-  rk4                                -> test_rk4_fourth_order_in_time, test_rk4_conserves_mass
+  rk4                                -> test_rk4_fourth_order_in_time, test_rk4_conserves_mass,
+                                        test_rk4_energy_factor_of_a_linear_mode
   init_aux                           -> test_init_aux_limit_relation
   mass_energy                        -> test_mass_energy_closed_forms
   mms_source                         -> test_mms_residual_second_order (+ the MMS sweep)
@@ -317,6 +318,46 @@ def test_rk4_conserves_mass(bc):
     q1 = oracle.rk4(g, q, b, 1e-4, 3)
     m1, _ = oracle.mass_energy(g, q1, b)
     assert abs(m1 - m0) <= 1e-14 * abs(m0) * 10
+
+
+@pytest.mark.parametrize("which", ["slow", "fast"])
+def test_rk4_energy_factor_of_a_linear_mode(which):
+    """One classical RK4 step multiplies a small eigenmode of the linearized
+    operator at rest (frequency w, y = w dt) by R(iy), R(z) = 1 + z + z^2/2 +
+    z^3/6 + z^4/24, so the mode's energy (quadratic in its amplitude) changes
+    by |R(iy)|^2 = 1 - y^6/72 + y^8/576 (textbook).  The mode: the linearized
+    rates at rest of exp(ikx) (pinned in test_linearized_closed_form),
+    h_t = -h0 ik' u, u_t = -(g + lam/(3 h0)) ik' h + lam/(3 h0) ik' eta,
+    w_t = lam/h0^2 (h - eta), eta_t = w, k' = sin(k dx)/dx."""
+    n, h0, lam, k, eps = 32, 1.0, 500.0, 3, 1e-5
+    g = W.Grid(n, 4, 0.0, 2 * math.pi, 0.0, 1.0, PER, PER, 9.81, lam)
+    dx = g.spacing()[0]
+    kt = math.sin(k * dx) / dx
+    A = np.array([[0, -h0 * 1j * kt, 0, 0],
+                  [-(g.g + lam / (3 * h0)) * 1j * kt, 0, 0, lam / (3 * h0) * 1j * kt],
+                  [lam / h0**2, 0, 0, -lam / h0**2],
+                  [0, 0, 1, 0]], dtype=complex)
+    ev, V = np.linalg.eig(A)
+    pos = [i for i in range(4) if ev[i].imag > 0]
+    m = min(pos, key=lambda i: ev[i].imag) if which == "slow" else max(pos, key=lambda i: ev[i].imag)
+    om, v = ev[m].imag, V[:, m] / np.abs(V[:, m]).max()
+    x = g.x_nodes()[None, :] * np.ones(g.shape)
+    mode = [np.real(c * np.exp(1j * k * x)) for c in v]
+    rest = np.zeros((5,) + g.shape)
+    rest[0] = h0
+    rest[4] = h0
+    q = rest.copy()
+    q[0] += eps * mode[0]
+    q[1] = eps * mode[1]
+    q[3] = eps * mode[2]
+    q[4] += eps * mode[3]
+    b = np.zeros(g.shape)
+    y = 1.5
+    _, e_rest = oracle.mass_energy(g, rest, b)
+    _, e0 = oracle.mass_energy(g, q, b)
+    _, e1 = oracle.mass_energy(g, oracle.rk4(g, q, b, y / om, 1), b)
+    factor = 1 - y**6 / 72 + y**8 / 576
+    assert abs((e1 - e_rest) / (e0 - e_rest) - factor) <= 1e-3 * (1 - factor), ((e1 - e_rest) / (e0 - e_rest), factor)
 
 
 def test_init_aux_limit_relation():
