@@ -61,3 +61,17 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert msg["requested_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_product_fails_loudly_without_library_or_gpu(monkeypatch):
+    """No fallback: a missing library raises, and so does a solver on a host
+    without a ROCm GPU (this container has none)."""
+    import torch
+    from paper_2601_02540_amd import workloads as W
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", os.path.join(os.path.dirname(binding.LIB_PATH), "missing_libsgn.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        binding.load_library()
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError, match="ROCm GPU"):
+            binding.Solver(W.Grid(8, 8, 0.0, 1.0, 0.0, 1.0))
