@@ -161,7 +161,7 @@ sgn_status sgn_step_relaxation(sgn_ctx* ctx, void* q, double dt, int64_t nsteps,
  * costs no pass over the state (totals summed in FP64, compensated,
  * deterministic; they agree with sgn_mass_energy to rounding).  series: device
  * memory, 2 nsteps doubles, FP64 whatever the dtype; not NULL unless nsteps is
- * 0 (a no-op).  Steps are
+ * 0 (a no-op).  nsteps < 2^30 (SGN_E_ARG otherwise).  Steps are
  * replayed from a captured graph; asynchronous.  Requires no source term
  * (SGN_E_UNSUPPORTED). */
 sgn_status sgn_step_totals(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* series);
