@@ -60,7 +60,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 STEP_TRAFFIC_BYTES_PER_NODE = (1193634395.4 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "5798bc0dcc42674757bd9f75d78e6060024a480582a2df549ff5f2ef4bc827f5"
+STEP_SOURCES_SHA256 = "34aff1f3e2ffec4a710a8cd525b06c4f448a207ed6f9adf1444a2958e9a06d91"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

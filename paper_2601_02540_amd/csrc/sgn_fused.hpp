@@ -33,7 +33,6 @@
 namespace sgn {
 
 constexpr int STEP_NODES = 512;  // owned nodes per tile (two per thread)
-
 constexpr int STEP_HALO = 4;     // one node per right-hand side of the step
 
 template <int TX>
