@@ -219,15 +219,16 @@ def ensemble(count: int = 256, seed: int = 4, sizes=(128, 256, 512, 1024), lam: 
 # ---------------------------------------------------------------------------
 # Two of the paper's own setups (their initial conditions are given in full).
 
-def gaussian_obstacle(nx: int = 1600, ny: Optional[int] = None, lam: float = 500.0) -> Problem:
+def gaussian_obstacle(nx: int = 1600, ny: Optional[int] = None, lam: float = 500.0, bc: int = PERIODIC) -> Problem:
     """Solitary wave over a Gaussian obstacle (Section "Solitary Wave over a Gaussian
     Obstacle"): periodic [-5,35] x [-10,10], bathymetry b = 0.1 exp(-(x^2+y^2)/2), still
     depth 0.2, a solitary wave of amplitude 0.0365 with its crest at x = -3 moving in +x
     (surface from the classical closed form, h = zeta - b, u from the closed form, v = 0).
     The paper's spacing 0.025 is nx = 1600, ny = 800; its scaling study uses nx = 2^n,
-    ny = nx/2 (square cells)."""
+    ny = nx/2 (square cells).  bc: both axes periodic (the setup) or reflecting (the
+    paper's semi-discrete energy check runs both)."""
     ny = nx // 2 if ny is None else ny
-    grid = Grid(nx, ny, -5.0, 35.0, -10.0, 10.0, PERIODIC, PERIODIC, 9.81, lam)
+    grid = Grid(nx, ny, -5.0, 35.0, -10.0, 10.0, bc, bc, 9.81, lam)
     X, Y = _mesh(grid)
     b = 0.1 * np.exp(-(X * X + Y * Y) / 2.0)
     zeta, u = classical_soliton(X, 0.0, 0.0365, 0.2, grid.g, -3.0)

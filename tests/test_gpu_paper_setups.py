@@ -7,7 +7,11 @@ oracle by exact windows (see gpu_util.check_windows) and by conservation:
   (10^8; 4 GB per FP64 state), reflecting walls;
 * the Riemann problem at the paper's size ([-600, 600], dx = 0.3, to
   t = 47.434): the mean state and the leading soliton's height against the
-  values the paper prints (tests/golden/riemann_problem.txt).
+  values the paper prints (tests/golden/riemann_problem.txt);
+* the paper's check of semi-discrete energy conservation (Section
+  "Semi-Discrete Energy Conservation"): along a run of the Gaussian-obstacle
+  setup, periodic and reflecting, the energy rate <d_q E, q_t>_M of the GPU's
+  right-hand side stays at rounding level.
 """
 
 import numpy as np
@@ -93,3 +97,25 @@ def test_riemann_problem_matches_the_paper():
     assert abs(m1 - m0) <= 1e-13 * abs(m0)
     plateau, hm = check_riemann(x, got[0][0], G)
     print(f"\nRiemann problem, {n} x 4 nodes, {ns} steps: h* = {plateau:.4f}, h_max = {hm:.4f}")
+
+
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.REFLECTING])
+def test_energy_rate_stays_at_rounding_along_gaussian_obstacle_run(bc):
+    p = W.gaussian_obstacle(400, bc=bc)  # spacing 0.1
+    g = p.grid
+    s = solver(g)
+    s.set_bathymetry(dev(p.b))
+    qd = dev(p.q0)
+    s.init_aux(qd)
+    dt = s.cfl_dt(qd, 0.5)
+    rows = []
+    for chunk in range(6):
+        if chunk:
+            s.step(qd, dt, 400)
+        mr, er = s.rates(qd)
+        _, _, sm, se = oracle.rates(g, host(qd), p.b)  # scales: sums of |terms| of each rate
+        rows.append((chunk * 400 * dt, mr / sm, er / se))
+        assert abs(mr) <= 1e-13 * sm and abs(er) <= 1e-13 * se, rows[-1]
+    s.check()
+    print("\n(t, mass rate / scale, energy rate / scale):", [tuple(round(v, 3) if i == 0 else float(f"{v:.2e}")
+                                                               for i, v in enumerate(r)) for r in rows])
