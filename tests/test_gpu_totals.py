@@ -60,6 +60,23 @@ def test_series_matches_per_step_totals(bc, ty, n):
     assert math.isclose(series[-1, 0], mo, rel_tol=1e-12) and math.isclose(series[-1, 1], eo, rel_tol=1e-12)
 
 
+@pytest.mark.parametrize("path", ["pairs", "stages"])
+def test_series_whatever_the_step_path(path):
+    """The recorded steps run on the step kernel whatever the selected path;
+    every path forms the same states, so the result equals sgn_step's."""
+    g, q0, b = problem(REF, 70, 41, seed=11)
+    dt = oracle.cfl_dt(g, q0, 0.5)
+    s = solver(g)
+    s.set_step_path(path)
+    s.set_bathymetry(dev(b))
+    qa, qb = dev(q0), dev(q0)
+    series = host(s.step_totals(qa, dt, 10))
+    s.step(qb, dt, 10)
+    assert np.array_equal(host(qa), host(qb))
+    m, e = s.mass_energy(qb)
+    assert math.isclose(series[-1, 0], m, rel_tol=1e-14) and math.isclose(series[-1, 1], e, rel_tol=1e-14)
+
+
 def test_series_repeated_calls_and_fp32():
     g, q0, b = problem(PER, 96, 64, seed=5)
     dt = oracle.cfl_dt(g, q0, 0.5)
