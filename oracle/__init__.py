@@ -21,13 +21,22 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgn_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
 # Plain evaluation order: no FMA contraction, no fast-math.
 BUILD_CMD = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
              "-o", _LIB, _SRC]
+# The same source with its OpenMP pragmas on: the threaded build used to time
+# the oracle on all host cores and to speed up large windows in the tests.
+# Its loops split only over disjoint outputs, so it forms the same bits as the
+# serial build (tests/test_oracle.py::test_threaded_build_bit_identical).
+BUILD_CMD_OMP = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+                 "-shared", "-o", _LIB_OMP, _SRC]
 
 
 def build() -> str:
     subprocess.check_call(BUILD_CMD)
+    subprocess.check_call(BUILD_CMD_OMP)
     return _LIB
 
 
@@ -39,15 +48,47 @@ class _OrcGrid(ctypes.Structure):
                 ("g", ctypes.c_double), ("lam", ctypes.c_double)]
 
 
-_lib = None
+_libs = {}
+_threaded = False
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+class threaded:
+    """Context manager: oracle calls inside it use the OpenMP build (all host
+    cores, or OMP_NUM_THREADS), which forms the same bits as the serial one."""
+
+    def __enter__(self):
+        global _threaded
+        self._prev = _threaded
+        _threaded = True
+        return self
+
+    def __exit__(self, *exc):
+        global _threaded
+        _threaded = self._prev
+        return False
+
+
+def threads_available() -> int:
+    """Threads the OpenMP build uses (its omp_get_max_threads())."""
+    _load(True)
+    lib = _libs[True]
+    return int(lib.orc_threads())
+
+
+def _load(omp=None):
+    omp = _threaded if omp is None else omp
+    path = _LIB_OMP if omp else _LIB
+    if omp not in _libs:
+        if not os.path.exists(path):
             build()
-        lib = ctypes.CDLL(_LIB)
+        if omp:
+            # Keep freed planes of up to 32 MiB (glibc's limit for this
+            # setting) in the heap, so that the threaded build's buffers are
+            # not faulted in page by page, serially, on every call.
+            libc = ctypes.CDLL(None)
+            libc.mallopt(-3, 1 << 25)   # M_MMAP_THRESHOLD
+            libc.mallopt(-1, 1 << 40)   # M_TRIM_THRESHOLD
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER
         d = ctypes.c_double
         dp = P(ctypes.c_double)
@@ -77,8 +118,12 @@ def _load():
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.orc_gauge_loss.argtypes = [gp, dp, dp, d, ctypes.c_int64, i64p, ctypes.c_int, dp, dp, dp, dp, dp]
         lib.orc_gauge_loss_grad.argtypes = [gp, dp, dp, d, ctypes.c_int64, i64p, ctypes.c_int, dp, dp, dp, dp]
-        _lib = lib
-    return _lib
+        lib.orc_threads.restype = ctypes.c_int
+        lib.orc_fsal35.argtypes = [gp, dp, dp, d, d, d, d, d, ctypes.c_int, ctypes.c_int64, dp, dp, i64p, i64p]
+        lib.orc_fsal35.restype = ctypes.c_int64
+        lib.orc_fsal35_tableau.argtypes = [dp, dp, dp, dp]
+        _libs[omp] = lib
+    return _libs[omp]
 
 
 def _grid(grid) -> _OrcGrid:
@@ -185,6 +230,29 @@ def rk4_relax(grid, q, b, dt: float, nsteps: int, t0: float = 0.0):
     gam = np.zeros(max(int(nsteps), 1))
     _load().orc_rk4_relax(ctypes.byref(_grid(grid)), _dp(q), _dp(b), dt, t0, int(nsteps), ctypes.byref(t_end), _dp(gam))
     return q, t_end.value, gam[:nsteps]
+
+
+def fsal35(grid, q, b, t0: float, t_end: float, dt0: float, rtol: float = 1e-6, atol: float = 1e-6,
+           adaptive: bool = True, max_attempts: int = 1_000_000):
+    """The adaptive five-stage third-order FSAL pair from t0 to t_end.  Returns
+    (q, t_reached, accepted, rejected, rec) with rec[n] = (h, err, accepted) of
+    attempt n."""
+    q = _state(q, grid).copy()
+    b = _plane(b, grid)
+    cap = int(max_attempts) if max_attempts < 10_000_000 else 10_000_000
+    rec = np.zeros((max(cap, 1), 3))
+    t_out = ctypes.c_double()
+    na, nr = ctypes.c_int64(), ctypes.c_int64()
+    n = _load().orc_fsal35(ctypes.byref(_grid(grid)), _dp(q), _dp(b), t0, t_end, dt0, rtol, atol, int(adaptive),
+                           cap, _dp(rec), ctypes.byref(t_out), ctypes.byref(na), ctypes.byref(nr))
+    return q, t_out.value, na.value, nr.value, rec[:n]
+
+
+def fsal35_tableau():
+    """(c, A, b, bh) of the adaptive pair: A is 6 x 6 (row 5 is the FSAL stage)."""
+    c, A, b, bh = np.zeros(6), np.zeros((6, 6)), np.zeros(6), np.zeros(6)
+    _load().orc_fsal35_tableau(_dp(c), _dp(A), _dp(b), _dp(bh))
+    return c, A, b, bh
 
 
 def init_aux(grid, q, b) -> np.ndarray:

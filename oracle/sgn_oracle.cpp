@@ -31,16 +31,24 @@
 //
 // Arithmetic is evaluated in the order the equations are printed; build with
 // -O2 -ffp-contract=off so that no fused multiply-add reorders it.
+// The OpenMP pragmas only matter for the threaded timing build (-fopenmp):
+// they split loops whose iterations write disjoint outputs, so every value is
+// formed by the same operations in the same order as in the serial build (a
+// test checks that both builds agree bit for bit); the reductions stay serial.
 // Every function is templated on the scalar so that the same source evaluates
 // in double (reference), float (to bound single-precision runs) and
 // std::complex<double> (complex-step directional derivatives for the adjoint
 // and manufactured-solution pins).
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstring>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 extern "C" {
 
@@ -130,7 +138,9 @@ Ops make_ops(const orc_grid& g) {
 // out = D_x f : D acting on the x index of every row j.
 template <class T>
 void apply_dx(const Ops& o, const T* f, T* out) {
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < o.N; ++k) out[k] = T(0);
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < o.ny; ++j)
     for (size_t e = 0; e < o.x.val.size(); ++e)
       out[(size_t)j * o.nx + o.x.row[e]] += T(o.x.val[e]) * f[(size_t)j * o.nx + o.x.col[e]];
@@ -139,8 +149,13 @@ void apply_dx(const Ops& o, const T* f, T* out) {
 // out = D_y f : D acting on the y index of every column i.
 template <class T>
 void apply_dy(const Ops& o, const T* f, T* out) {
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < o.N; ++k) out[k] = T(0);
+  // (threaded build: a static schedule gives every thread the same columns i
+  // for every entry e, so each output still sums its entries in order e)
+#pragma omp parallel
   for (size_t e = 0; e < o.y.val.size(); ++e)
+#pragma omp for schedule(static) nowait
     for (int i = 0; i < o.nx; ++i)
       out[(size_t)o.y.row[e] * o.nx + i] += T(o.y.val[e]) * f[(size_t)o.y.col[e] * o.nx + i];
 }
@@ -290,6 +305,7 @@ void rhs_impl(const orc_grid& gr, const Ops& o, const T* q, const T* b, double t
 
   // Pointwise (componentwise) products.
   std::vector<T> H(N), hH(N), u2(N), v2(N), hu(N), hv(N), huv(N), uv(N), e2h(N), huw(N), hvw(N), uw(N), vw(N), hw(N);
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < N; ++k) {
     H[k] = h[k] + b[k];
     hH[k] = h[k] * H[k];
@@ -335,6 +351,7 @@ void rhs_impl(const orc_grid& gr, const Ops& o, const T* q, const T* b, double t
   apply_dy(o, e2h.data(), Dye2h.data());
   apply_dy(o, hvw.data(), Dyhvw.data());
 
+#pragma omp parallel for schedule(static)
   for (int j = 0; j < o.ny; ++j) {
     for (int i = 0; i < o.nx; ++i) {
       const size_t k = (size_t)j * o.nx + i;
@@ -373,6 +390,7 @@ void rhs_impl(const orc_grid& gr, const Ops& o, const T* q, const T* b, double t
   }
 
   if (src == 1) {
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < o.ny; ++j)
       for (int i = 0; i < o.nx; ++i) {
         double S[5];
@@ -390,13 +408,138 @@ void rk4_step_impl(const orc_grid& gr, const Ops& o, T* q, const T* b, double dt
   std::vector<T> k1(M), k2(M), k3(M), k4(M), Y(M);
   const T Tdt = T(dt);
   rhs_impl(gr, o, q, b, t, src, k1.data());
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt / T(2) * k1[k];
   rhs_impl(gr, o, Y.data(), b, t + dt / 2, src, k2.data());
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt / T(2) * k2[k];
   rhs_impl(gr, o, Y.data(), b, t + dt / 2, src, k3.data());
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < M; ++k) Y[k] = q[k] + Tdt * k3[k];
   rhs_impl(gr, o, Y.data(), b, t + dt, src, k4.data());
+#pragma omp parallel for schedule(static)
   for (size_t k = 0; k < M; ++k) q[k] = q[k] + Tdt * (k1[k] + T(2) * k2[k] + T(2) * k3[k] + k4[k]) / T(6);
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive Runge-Kutta pair of the kind the paper integrates with (Section
+// "Numerical Experiments": explicit, third order, five stages, first same as
+// last, an embedded error estimator driving the step size, relative and
+// absolute tolerances 1e-6).  The paper names the method by citation only, so
+// the coefficients are this project's reading, a pair of that shape:
+//   * main method, order 3, five stages, stages chained through the
+//     subdiagonal only: Y_{i+1} = y_n + h c_{i+1} k_i, with
+//     c = (0, 1/3, 3/4, 4/5, 3071/3720) and the weights b below, which make
+//     the stability polynomial 1 + z + z^2/2 + z^3/6 + z^4/31 + z^5/163 (stable
+//     on the imaginary axis up to |y| ~ 3.9, where the conservative
+//     semi-discretization's spectrum lies);
+//   * embedded method, order 2, on the five stages and the first-same-as-last
+//     stage k6 = f(y_{n+1}) (abscissa 1, row b): weights bh below;
+//   * error estimate y_{n+1} - yh_{n+1} = h sum_i (b_i - bh_i) k_i, measured in
+//     the root-mean-square norm over all 5N values, each scaled by
+//     atol + rtol max(|y_n|, |y_{n+1}|);
+//   * PI step-size control (Hairer-Wanner, Solving ODEs II, Section IV.2):
+//     accepted when err <= 1, next step h 0.9 err^(-0.7/3) errp^(0.4/3)
+//     limited to [0.2, 5] h (to [0.2, 1] h right after a rejection), errp the
+//     last accepted err (at least 1e-4, 1 at the start); rejected steps are
+//     retried with h max(0.2, 0.9 err^(-1/3)); the last step is cut (or
+//     stretched by at most a relative 1e-10) to end at t_end exactly.
+struct Fsal35 {
+  double c[6];
+  double a[6][6];
+  double b[6];   // main weights (b[5] = 0: the last stage only serves the estimate)
+  double bh[6];  // embedded weights
+};
+
+Fsal35 fsal35_tableau() {
+  Fsal35 t{};
+  const double c[6] = {0.0, 1.0 / 3.0, 3.0 / 4.0, 4.0 / 5.0, 3071.0 / 3720.0, 1.0};
+  const double b[6] = {7200668.0 / 46553289.0, 1701.0 / 5053.0, 6098.0 / 15159.0, 350.0 / 5053.0,
+                       18600.0 / 500573.0, 0.0};
+  const double bh[6] = {7502453.0 / 46553289.0, 1701.0 / 5053.0, 6098.0 / 15159.0, 350.0 / 5053.0, 0.0,
+                        15355.0 / 500573.0};
+  for (int i = 0; i < 6; ++i) {
+    t.c[i] = c[i];
+    t.b[i] = b[i];
+    t.bh[i] = bh[i];
+  }
+  for (int i = 1; i < 5; ++i) t.a[i][i - 1] = c[i];  // Y_{i+1} = y_n + h c_{i+1} k_i
+  for (int j = 0; j < 5; ++j) t.a[5][j] = b[j];      // the FSAL stage is f(y_{n+1})
+  return t;
+}
+
+// Runs the pair from t0 to t_end (or for max_attempts attempts).  adaptive = 0:
+// fixed steps h = dt0 (the last one cut to reach t_end), every step accepted
+// (the estimate is still formed and recorded).  rec (may be NULL) receives
+// (h, err, accepted) per attempt.  Returns the number of attempts.
+int64_t fsal35_run(const orc_grid& gr, const Ops& o, double* y, const double* b, double t0, double t_end,
+                   double dt0, double rtol, double atol, int adaptive, int64_t max_attempts, double* rec,
+                   double* t_out, int64_t* n_acc, int64_t* n_rej) {
+  const Fsal35 tb = fsal35_tableau();
+  const size_t M = 5 * o.N;
+  std::vector<std::vector<double>> k(6, std::vector<double>(M));
+  std::vector<double> Y(M), ynew(M);
+  rhs_impl(gr, o, y, b, t0, 0, k[0].data());
+  double t = t0, dt = dt0, errp = 1.0;
+  bool after_reject = false;
+  int64_t att = 0, acc = 0, rej = 0;
+  const double safety = 0.9, facmin = 0.2, facmax = 5.0, kexp = 3.0;
+  while (t < t_end && att < max_attempts) {
+    // the last step ends exactly at t_end (also when rounding left it a hair longer than dt)
+    const double h = (t_end - t <= dt * (1.0 + 1e-10)) ? t_end - t : dt;
+    for (int i = 1; i < 5; ++i) {
+      for (size_t m = 0; m < M; ++m) {
+        double sum = 0.0;
+        for (int j = 0; j < i; ++j) sum += tb.a[i][j] * k[j][m];
+        Y[m] = y[m] + h * sum;
+      }
+      rhs_impl(gr, o, Y.data(), b, t + tb.c[i] * h, 0, k[i].data());
+    }
+    for (size_t m = 0; m < M; ++m) {
+      double sum = 0.0;
+      for (int j = 0; j < 5; ++j) sum += tb.b[j] * k[j][m];
+      ynew[m] = y[m] + h * sum;
+    }
+    rhs_impl(gr, o, ynew.data(), b, t + h, 0, k[5].data());
+    Neumaier sq;
+    for (size_t m = 0; m < M; ++m) {
+      double e = 0.0;
+      for (int j = 0; j < 6; ++j) e += (tb.b[j] - tb.bh[j]) * k[j][m];
+      e *= h;
+      const double scale = atol + rtol * std::max(std::fabs(y[m]), std::fabs(ynew[m]));
+      sq.add((e / scale) * (e / scale));
+    }
+    const double err = std::sqrt(sq.value() / (double)M);
+    const bool ok = !adaptive || err <= 1.0;
+    if (rec) {
+      rec[3 * att + 0] = h;
+      rec[3 * att + 1] = err;
+      rec[3 * att + 2] = ok ? 1.0 : 0.0;
+    }
+    ++att;
+    if (ok) {
+      std::memcpy(y, ynew.data(), M * sizeof(double));
+      std::swap(k[0], k[5]);  // first same as last
+      t = (h == t_end - t) ? t_end : t + h;
+      ++acc;
+      if (adaptive) {
+        double fac = safety * std::pow(err, -0.7 / kexp) * std::pow(errp, 0.4 / kexp);
+        fac = std::min(fac, after_reject ? 1.0 : facmax);
+        fac = std::max(fac, facmin);
+        dt = h * fac;
+        errp = std::max(err, 1e-4);
+      }
+      after_reject = false;
+    } else {
+      ++rej;
+      dt = h * std::max(facmin, safety * std::pow(err, -1.0 / kexp));
+      after_reject = true;
+    }
+  }
+  *t_out = t;
+  *n_acc = acc;
+  *n_rej = rej;
+  return att;
 }
 
 // Energy density E = h ((u^2+v^2)/2 + e), e = w^2/6 + g/2 (h + 2b) + lambda/6 (eta/h - 1)^2.
@@ -1022,6 +1165,34 @@ void orc_gauge_loss_grad(const orc_grid* g, const double* zeta0, const double* b
     grad_zeta0[k] = h0b;
     grad_b[k] = bb[k] - h0b;
   }
+}
+
+// The adaptive pair (see fsal35_run): q is advanced in place.
+int64_t orc_fsal35(const orc_grid* g, double* q, const double* b, double t0, double t_end, double dt0, double rtol,
+                   double atol, int adaptive, int64_t max_attempts, double* rec, double* t_out, int64_t* n_acc,
+                   int64_t* n_rej) {
+  Ops o = make_ops(*g);
+  return fsal35_run(*g, o, q, b, t0, t_end, dt0, rtol, atol, adaptive, max_attempts, rec, t_out, n_acc, n_rej);
+}
+
+// The pair's coefficients: c[6], a[36] (row-major), b[6], bh[6].
+void orc_fsal35_tableau(double* c, double* a, double* b, double* bh) {
+  const Fsal35 t = fsal35_tableau();
+  for (int i = 0; i < 6; ++i) {
+    c[i] = t.c[i];
+    b[i] = t.b[i];
+    bh[i] = t.bh[i];
+    for (int j = 0; j < 6; ++j) a[6 * i + j] = t.a[i][j];
+  }
+}
+
+// Threads the build runs its loops on (1 for the serial build).
+int orc_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 }  // extern "C"

@@ -484,3 +484,24 @@ def test_solitary_second_order():
     orders = np.log2(errs[:-1] / errs[1:])
     assert np.all(orders[-1] > 1.85), orders
     assert np.all(orders > 1.6), orders
+
+
+# ---------------------------------------------------------------------------
+# The threaded (OpenMP) build of the same source, used to time the oracle on all
+# host cores and to step large windows: its loops split over disjoint outputs
+# only, so it must form exactly the serial build's bits.
+
+@pytest.mark.parametrize("bcx,bcy", [(PER, PER), (REF, REF), (PER, REF)])
+def test_threaded_build_bit_identical(bcx, bcy):
+    g = W.Grid(97, 61, -1.0, 2.0, 0.5, 2.0, bcx, bcy, 9.81, 500.0)
+    q, b = W.random_state(g, 7, b_scale=0.05)
+    q[1:4] *= 0.1
+    dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
+    serial = (oracle.rhs(g, q, b), oracle.rk4(g, q, b, dt, 3), oracle.init_aux(g, q, b),
+              oracle.rk4(g, q, b, dt, 2, 0.1, 1))
+    with oracle.threaded():
+        par = (oracle.rhs(g, q, b), oracle.rk4(g, q, b, dt, 3), oracle.init_aux(g, q, b),
+               oracle.rk4(g, q, b, dt, 2, 0.1, 1))
+    for a, c in zip(serial, par):
+        assert np.array_equal(a, c)
+    assert oracle.threads_available() >= 1
