@@ -10,10 +10,19 @@ the two-kernel pair path or the four-kernel stage path); the value is RK-stage
 cell-updates per second, nx * ny * 4 * steps / seconds, with all inputs
 resident in HBM before the timed region starts.
 
+The timed region is `--repeats` runs of `--steps` steps each (median
+reported), after `--warmup` untimed steps; the HIP graphs the timed calls
+replay are instantiated before the first timing event.  The roofline entry
+is the step kernel's: the method's 11 values per node and step (88 B in FP64)
+over the mean launch duration in the timed region, against the 8 TB/s HBM
+peak, with the FP64 arithmetic rate beside it.
+
 The same run is repeated with reflecting walls and with FP32 storage and
 arithmetic (energy and mass still reduced in FP64), reported under
-"variants".  The CPU oracle times one RK4 step of the same workload on the
-host as a baseline.
+"variants".  Each 4096^2 run's mass and energy after --drift-steps steps are
+compared with the FP64 oracle's over the same steps (each side initializes
+the workload itself).  The CPU oracle is timed on the host as a baseline: its
+threaded build on every usable core and its serial build on one.
 
 Prints one JSON line.
 """
@@ -57,14 +66,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
 # they had when the counters were taken.
-STEP_TRAFFIC_BYTES_PER_NODE = (1193634395.4 + 671088640.0) / 16777216
+STEP_TRAFFIC_BYTES_PER_NODE = (1185575387.4 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "34aff1f3e2ffec4a710a8cd525b06c4f448a207ed6f9adf1444a2958e9a06d91"
+STEP_SOURCES_SHA256 = "f1a4b1c069e5640ee73d5f1a722a734e73327a2ad367f490d7961637c5d4e094"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
-ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation", "totals"}
+ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation", "totals",
+                "adaptive"}
 
 
 def log(msg):
@@ -88,7 +98,12 @@ def lake_at_rest_energy(grid, b, mass):
     return 0.5 * grid.g * (M * (H * H - b * b)).sum()
 
 
-def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
+def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, repeats=1, drift_steps=0):
+    """Times `repeats` runs of `steps` RK4 steps (after `warmup` untimed ones) with
+    HIP events on the solver's stream; every graph a timed call replays is
+    instantiated before the first event.  With drift_steps > 0, also records
+    mass and energy over the first drift_steps steps from the initial state
+    (step kernel epilogue) for the comparison with the oracle."""
     import numpy as np
     import torch
     from paper_2601_02540_amd.binding import Solver
@@ -105,32 +120,48 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
     s.init_aux(q)
     dt = s.cfl_dt(q, 0.5)
     m0, e0 = s.mass_energy(q)
-    log(f"[{label}] dt={dt:.6e} warmup={warmup}")
+    series = None
+    if drift_steps > 0:
+        qd = q.clone()
+        series = s.step_totals(qd, dt, drift_steps).cpu().numpy()
+        del qd
+    log(f"[{label}] dt={dt:.6e} warmup={warmup} repeats={repeats}")
+    s.prepare_step(q, dt, warmup)
+    s.prepare_step(q, dt, steps)
     if warmup > 0:
         s.step(q, dt, warmup)
     torch.cuda.synchronize()
     stream = s.stream
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    t_start.record(stream)
-    s.step(q, dt, steps, t0=warmup * dt)
-    t_end.record(stream)
-    t_end.synchronize()
-    torch.cuda.synchronize()
-    sec = t_start.elapsed_time(t_end) / 1e3
+    secs = []
+    t = warmup * dt
+    for _ in range(repeats):
+        t_start = torch.cuda.Event(enable_timing=True)
+        t_end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start.record(stream)
+        s.step(q, dt, steps, t0=t)
+        t_end.record(stream)
+        t_end.synchronize()
+        torch.cuda.synchronize()
+        secs.append(t_start.elapsed_time(t_end) / 1e3)
+        t += steps * dt
+    sec = float(np.median(secs))
+    # per-launch durations of the path's kernels (direct launches with HIP events between them),
+    # right after the timed runs: after an idle spell the GPU's first launches run up to 30% slower
+    ms = s.profile_stages(q, dt, 10)
     s.check()
     m1, e1 = s.mass_energy(q)
     cells = grid.nx * grid.ny
     esize = 8 if dtype == torch.float64 else 4
     launch_s = sec / (launches * steps)
     achieved = values / launches * esize * cells / launch_s / 1e9
-    # per-mode durations of the four stage kernels (direct launches with HIP events)
-    ms = s.profile_stages(q, dt, 5)
     e_rest = lake_at_rest_energy(grid, problem.b.astype(np.float64), m0)
     res = {
         "value": cells * 4 * steps / sec,
         "sec": sec,
         "ms_per_step": sec / steps * 1e3,
+        "ms_per_step_repeats": [x / steps * 1e3 for x in secs],
+        "repeats": repeats,
         "dt": dt,
         "stage_launch_us": launch_s * 1e6,
         "achieved_GBs": achieved,
@@ -144,8 +175,12 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None):
         "energy_drift_rel": (e1 - e0) / abs(e0),
         "energy_drift_rel_to_excess": (e1 - e0) / abs(e0 - e_rest),
         "energy_final": e1,
+        "steps_total": warmup + repeats * steps,
     }
-    log(f"[{label}] {res['value']:.4e} cell-stage/s  {res['ms_per_step']:.3f} ms/step  "
+    if series is not None:
+        res["drift_series"] = {"steps": drift_steps, "mass0": m0, "energy0": e0,
+                               "mass": float(series[-1, 0]), "energy": float(series[-1, 1])}
+    log(f"[{label}] {res['value']:.4e} cell-stage/s  {res['ms_per_step']:.3f} ms/step (median of {repeats})  "
         f"{achieved:.0f} GB/s ({100 * res['frac']:.1f}% of HBM peak)  dE/E={res['energy_drift_rel']:.3e}")
     s.close()
     del q, b
@@ -430,26 +465,161 @@ def run_totals(problem, steps, warmup, tile_y):
     return res
 
 
+def run_adaptive(nx, t_end, label, rtol=1e-6, atol=1e-6):
+    """The adaptive five-stage FSAL pair at the paper's tolerances on the paper's
+    Gaussian-obstacle setup (nx x nx/2, spacing 40/nx), from t = 0 to t_end,
+    beside classical RK4 at the fixed CFL-0.5 step over the same interval.
+    Right-hand-side evaluations: 5 per attempt (the FSAL stage is the next
+    attempt's first), 4 per RK4 step."""
+    import numpy as np
+    import torch
+    from paper_2601_02540_amd import workloads as W
+    from paper_2601_02540_amd.binding import Solver
+    p = W.gaussian_obstacle(nx)
+    g = p.grid
+    s = Solver(g, torch.float64)
+    b = torch.from_numpy(p.b).cuda()
+    q0 = torch.from_numpy(p.q0).cuda()
+    s.set_bathymetry(b)
+    s.init_aux(q0)
+    dt_cfl = s.cfl_dt(q0, 0.5)
+    m0, e0 = s.mass_energy(q0)
+    q = q0.clone()
+    s.step_adaptive(q, 0.0, 4 * dt_cfl, dt_cfl, rtol, atol)  # warm-up (buffers, graph)
+    q.copy_(q0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = s.step_adaptive(q, 0.0, t_end, dt_cfl, rtol, atol)
+    wall = time.perf_counter() - t0
+    m1, e1 = s.mass_energy(q)
+    # fixed-step RK4 over the same interval
+    n_rk4 = math.ceil(t_end / dt_cfl)
+    qr = q0.clone()
+    s.prepare_step(qr, t_end / n_rk4, n_rk4)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s.step(qr, t_end / n_rk4, n_rk4)
+    torch.cuda.synchronize()
+    wall_rk4 = time.perf_counter() - t1
+    _, er = s.mass_energy(qr)
+    cells = g.nx * g.ny
+    diff = float(torch.max(torch.abs(q[0] - qr[0])))
+    out = {"grid": [g.nx, g.ny], "t_end": t_end, "rtol": rtol, "atol": atol, "wall_s": wall,
+           "accepted": res["accepted"], "rejected": res["rejected"],
+           "mean_step": t_end / res["accepted"], "cfl_step": dt_cfl,
+           "ms_per_attempt": wall / res["attempts"] * 1e3,
+           "rhs_evals_per_s": cells * 5 * res["attempts"] / wall,
+           "mass_drift_rel": (m1 - m0) / abs(m0), "energy_drift_rel": (e1 - e0) / abs(e0),
+           "rk4_fixed": {"steps": n_rk4, "wall_s": wall_rk4, "rhs_evals_per_s": cells * 4 * n_rk4 / wall_rk4,
+                         "energy_drift_rel": (er - e0) / abs(e0)},
+           "max_abs_h_diff_vs_rk4": diff}
+    log(f"[{label}] {res['accepted']} accepted / {res['rejected']} rejected steps to t = {t_end} "
+        f"(mean step {out['mean_step']:.3e}, CFL step {dt_cfl:.3e}) in {wall:.3f} s; "
+        f"RK4 at the CFL step: {n_rk4} steps in {wall_rk4:.3f} s")
+    s.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def torch_f64():
     import torch
     return torch.float64
 
 
-def cpu_baseline(problem, steps=2):
-    """The FP64 oracle (single thread, as written) on the same workload: two RK4
-    steps, about 20 s of host time."""
-    import numpy as np
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def oracle_child(spec):
+    """Child-process leg (bench.py --oracle-child JSON): the FP64 oracle on the
+    benchmark workload.  For each boundary type in spec["bcs"]: the oracle's own
+    initialization and CFL step, totals at step 0 and after spec["drift_steps"]
+    steps of its threaded build (timed: the all-core baseline), and on the first
+    boundary type also spec["serial_steps"] steps of the serial build (timed:
+    the single-thread baseline).  Prints one JSON line."""
     import oracle
-    oracle.build() if not os.path.exists(oracle._LIB) else None
-    q = oracle.init_aux(problem.grid, problem.q0, problem.b)
-    dt = oracle.cfl_dt(problem.grid, q, 0.5)
-    t0 = time.perf_counter()
-    oracle.rk4(problem.grid, q, problem.b, dt, steps)
-    sec = time.perf_counter() - t0
-    cells = problem.grid.nx * problem.grid.ny
-    return {"value": cells * 4 * steps / sec, "unit": "cell-stage/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 step(s) of the same {problem.grid.nx}x{problem.grid.ny} FP64 workload "
-                      f"({sec:.1f} s, single-threaded C++ -O2 -ffp-contract=off)"}
+    from paper_2601_02540_amd import workloads as W
+    out = {"threads": oracle.threads_available(), "bcs": {}}
+    for k, name in enumerate(spec["bcs"]):
+        p = W.random_phase_large(spec["n"], W.PERIODIC if name == "periodic" else W.REFLECTING, seed=3)
+        g = p.grid
+        q = oracle.init_aux(g, p.q0, p.b)
+        dt = oracle.cfl_dt(g, q, 0.5)
+        m0, e0 = oracle.mass_energy(g, q, p.b)
+        entry = {"dt": dt, "mass0": m0, "energy0": e0, "cells": g.nx * g.ny}
+        if k == 0 and spec["serial_steps"] > 0:
+            t0 = time.perf_counter()
+            oracle.rk4(g, q, p.b, dt, spec["serial_steps"])
+            entry["serial_s"] = time.perf_counter() - t0
+            entry["serial_steps"] = spec["serial_steps"]
+        m = spec["drift_steps"]
+        with oracle.threaded():
+            t0 = time.perf_counter()
+            qm = oracle.rk4(g, q, p.b, dt, m)
+            entry["threaded_s"] = time.perf_counter() - t0
+        entry["drift_steps"] = m
+        entry["mass"], entry["energy"] = oracle.mass_energy(g, qm, p.b)
+        out["bcs"][name] = entry
+    print(json.dumps(out), flush=True)
+
+
+def run_oracle_child(n, bcs, drift_steps, serial_steps):
+    """Runs oracle_child in a fresh process.  glibc would return every freed
+    plane to the system and fault it in again, page by page and serially, on
+    the next call; the child keeps freed memory in its heap instead (malloc
+    thresholds set in its environment), which only changes where the oracle's
+    buffers come from."""
+    import subprocess
+    env = dict(os.environ, MALLOC_MMAP_THRESHOLD_=str(1 << 40), MALLOC_TRIM_THRESHOLD_=str(1 << 42))
+    spec = {"n": n, "bcs": bcs, "drift_steps": drift_steps, "serial_steps": serial_steps}
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", json.dumps(spec)],
+                       env=env, capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline(orc):
+    """The oracle as it stands, timed on the host: the threaded build over all
+    usable cores (value) and the serial build on one (single_thread)."""
+    first = next(iter(orc["bcs"].values()))
+    cells = first["cells"]
+    thr = cells * 4 * first["drift_steps"] / first["threaded_s"]
+    res = {"value": thr, "unit": "cell-stage/s", "cores": orc["threads"], "kind": "oracle",
+           "sample": f"{first['drift_steps']} RK4 steps of the same {int(math.isqrt(cells))}^2 FP64 workload "
+                     f"({first['threaded_s']:.1f} s; C++ -O2 -ffp-contract=off, OpenMP build, "
+                     f"{orc['threads']} threads)", **cpu_info()}
+    if "serial_s" in first:
+        res["single_thread"] = {"value": cells * 4 * first["serial_steps"] / first["serial_s"], "cores": 1,
+                                "sample": f"{first['serial_steps']} RK4 steps, serial build "
+                                          f"({first['serial_s']:.1f} s)"}
+    return res
+
+
+def vs_oracle(gpu_res, orc_entry):
+    """Totals after the same number of steps from each side's own initialization
+    of the workload: GPU (any storage type) against the FP64 oracle."""
+    d = gpu_res.get("drift_series")
+    if d is None or orc_entry is None or d["steps"] != orc_entry["drift_steps"]:
+        return None
+    return {"steps": d["steps"],
+            "gpu_energy_drift_rel": (d["energy"] - d["energy0"]) / abs(d["energy0"]),
+            "oracle_energy_drift_rel": (orc_entry["energy"] - orc_entry["energy0"]) / abs(orc_entry["energy0"]),
+            "energy_diff_rel": (d["energy"] - orc_entry["energy"]) / abs(orc_entry["energy"]),
+            "mass_diff_rel": (d["mass"] - orc_entry["mass"]) / abs(orc_entry["mass"]),
+            "gpu_mass_drift_rel": (d["mass"] - d["mass0"]) / abs(d["mass0"]),
+            "oracle_mass_drift_rel": (orc_entry["mass"] - orc_entry["mass0"]) / abs(orc_entry["mass0"])}
 
 
 def step_sources_unchanged():
@@ -461,26 +631,27 @@ def step_sources_unchanged():
     return h.hexdigest() == STEP_SOURCES_SHA256
 
 
-def roofline(path, res, cells):
-    """Roofline entry of the main run's dominant kernel.  The step kernel moves
-    only the method's own 11 values per node and step; its arithmetic intensity
-    (FLOPS_PER_NODE_STEP / 88 B) sits at the FP64 ridge of the MI355X and it is
-    limited on chip (FP64 issue and LDS), so it is reported against the FP64
-    vector peak, with its HBM figures beside it.  The pair and stage kernels
-    are reported against HBM."""
+def roofline(path, res, cells, esize=8):
+    """Roofline entry of the main run's dominant kernel, against HBM: the
+    algorithmic bytes of one launch (the method's own values per node, see
+    PATHS) over the mean launch duration inside the timed region.  For the
+    step kernel the FP64 arithmetic rate (FLOPS_PER_NODE_STEP per node) is
+    reported beside it."""
     values, launches = PATHS[path]
     traffic = None
-    if path == "fused" and cells == 4096 * 4096 and res["tile_y"] in (None, 16) and step_sources_unchanged():
+    if path == "fused" and esize == 8 and cells == 4096 * 4096 and res["tile_y"] in (None, 16) and \
+            step_sources_unchanged():
         traffic = STEP_TRAFFIC_BYTES_PER_NODE * cells
-    common = {"kernel": KERNELS[path], "traffic": traffic, "traffic_unit": "bytes per launch",
-              "algorithmic_bytes_per_launch_per_node": values / launches * 8,
-              "algorithmic_bytes_per_step_per_node": values * 8}
+    out = dict(bound="hbm", achieved=res["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=res["frac"],
+               traffic=traffic, kernel=KERNELS[path], traffic_unit="bytes per launch",
+               launch_us=res["stage_launch_us"],
+               algorithmic_bytes_per_launch_per_node=values / launches * esize,
+               algorithmic_bytes_per_step_per_node=values * esize)
     if path == "fused":
         tflops = FLOPS_PER_NODE_STEP * cells / (res["stage_launch_us"] * 1e-6) / 1e12
-        return dict(bound="alu", achieved=tflops, peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=tflops / FP64_VECTOR_PEAK_TFLOPS, flops_per_node_step=FLOPS_PER_NODE_STEP,
-                    hbm_achieved_GBs=res["achieved_GBs"], hbm_frac=res["frac"], **common)
-    return dict(bound="hbm", achieved=res["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=res["frac"], **common)
+        out.update(fp64_achieved_TFLOPs=tflops, fp64_peak_TFLOPs=FP64_VECTOR_PEAK_TFLOPS,
+                   fp64_frac=tflops / FP64_VECTOR_PEAK_TFLOPS, flops_per_node_step=FLOPS_PER_NODE_STEP)
+    return out
 
 
 def calib_copy(nbytes):
@@ -507,14 +678,23 @@ def main():
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
                     help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation,"
-                         "totals "
-                         "(default all)")
+                         "totals,adaptive (default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
     ap.add_argument("--long-dam-break", action="store_true",
                     help="also run the 10^8-node cylindrical dam break to t = 300 (several minutes)")
+    ap.add_argument("--repeats", type=int, default=5, help="timed repeats of --steps steps (median reported)")
+    ap.add_argument("--drift-steps", type=int, default=10,
+                    help="steps over which the 4096^2 runs' totals are compared with the FP64 oracle's (0: skip)")
+    ap.add_argument("--oracle-serial-steps", type=int, default=2,
+                    help="steps of the serial oracle in the single-thread CPU baseline")
+    ap.add_argument("--oracle-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.oracle_child is not None:
+        oracle_child(json.loads(args.oracle_child))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -537,7 +717,8 @@ def main():
     log(f"[bench] generating {n}x{n} workload")
     prob = W.random_phase_large(n, W.PERIODIC, seed=3)
     P, T = args.path, args.tile_y
-    main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64", P, T)
+    R, DS = max(args.repeats, 1), max(args.drift_steps, 0)
+    main_res = run_gpu(prob, torch.float64, args.steps, args.warmup, "periodic f64", P, T, R, DS)
 
     variants = {}
     chosen = set() if args.no_variants else (ALL_VARIANTS if args.variants == "all" else set(args.variants.split(",")))
@@ -545,27 +726,31 @@ def main():
     if unknown:
         raise SystemExit(f"unknown variants: {sorted(unknown)}; choose from {sorted(ALL_VARIANTS)}")
     if "f32" in chosen:
-        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T)
+        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T, R, DS)
         variants["periodic_f32"]["energy_diff_vs_f64_rel"] = (
             (variants["periodic_f32"]["energy_final"] - main_res["energy_final"]) / abs(main_res["energy_final"]))
     if "reflecting" in chosen:
         probr = W.random_phase_large(n, W.REFLECTING, seed=3)
-        variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T)
-        variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T)
+        variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T,
+                                             R, DS)
+        variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T,
+                                             R, DS)
     if "ensemble" in chosen:
         variants["ensemble_256_f32"] = run_ensemble(256, args.ensemble_steps, 4, torch.float32, "ensemble f32",
                                                     "pairs" if P == "pairs" else "fused")
     if "small" in chosen:
         small = W.gaussian_bump_periodic(64, seed=1)
-        variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T)
+        variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T, R)
         sol = W.soliton_over_bathymetry(512, seed=2)
-        variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T)
+        variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T, R)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
     if "relaxation" in chosen:
         variants["relaxation_f64"] = run_relaxation(prob, min(args.steps, 200), 8, P, T)
     if "totals" in chosen:
         variants["recorded_totals_f64"] = run_totals(prob, min(args.steps, 200), 8, T)
+    if "adaptive" in chosen:
+        variants["adaptive_fsal_gaussian_obstacle_1600x800"] = run_adaptive(1600, 0.5, "adaptive pair 1600x800")
     if "paper" in chosen:
         variants["paper_setups"] = run_paper_setups(P, T)
     if args.long_dam_break:
@@ -574,13 +759,20 @@ def main():
         for other in sorted(PATHS):
             if other != P:
                 variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
-                                                            f"periodic f64 {other}", other, T)
+                                                            f"periodic f64 {other}", other, T, R)
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on two steps of the same workload")
-        cpu = cpu_baseline(prob)
-        log(f"[bench] cpu {cpu['value']:.3e} cell-stage/s")
+    if not args.no_cpu_baseline or DS > 0:
+        bcs = ["periodic"] + (["reflecting"] if "reflecting_f64" in variants and DS > 0 else [])
+        log(f"[bench] FP64 oracle on the same workload ({', '.join(bcs)}): {DS} threaded steps, "
+            f"{0 if args.no_cpu_baseline else args.oracle_serial_steps} serial")
+        orc = run_oracle_child(n, bcs, max(DS, 1), 0 if args.no_cpu_baseline else args.oracle_serial_steps)
+        if not args.no_cpu_baseline:
+            cpu = cpu_baseline(orc)
+            log(f"[bench] cpu {cpu['value']:.3e} cell-stage/s on {cpu['cores']} threads")
+        for name, res in [("periodic", main_res)] + [(k.split("_")[0], v) for k, v in variants.items()
+                                                     if k in ("periodic_f32", "reflecting_f64", "reflecting_f32")]:
+            res["energy_vs_oracle"] = vs_oracle(res, orc["bcs"].get(name))
 
     cells = n * n
     line = {
@@ -601,12 +793,16 @@ def main():
                    "nx": n, "ny": n, "cells": cells, "bc": "periodic", "lambda": 500.0, "g": 9.81,
                    "dt": main_res["dt"], "parallelism": "single GPU"},
         "roofline": roofline(P, main_res, cells),
+        "repeats": R,
+        "ms_per_step_repeats": main_res["ms_per_step_repeats"],
+        "energy_vs_oracle": main_res.get("energy_vs_oracle"),
         "cpu_baseline": cpu,
         "energy_drift_rel": main_res["energy_drift_rel"],
         "energy_drift_rel_to_excess": main_res["energy_drift_rel_to_excess"],
         "mass_drift_rel": main_res["mass_drift_rel"],
         "kernel_ms": main_res["kernel_ms"],
-        "variants": {k: {kk: vv for kk, vv in v.items() if kk not in ("energy_final",)} for k, v in variants.items()},
+        "variants": {k: {kk: vv for kk, vv in v.items() if kk not in ("energy_final", "drift_series")}
+                     for k, v in variants.items()},
     }
     print(json.dumps(line), flush=True)
 

@@ -138,6 +138,14 @@ sgn_status sgn_rhs(sgn_ctx* ctx, const void* q, void* dq, double t);
  * are replayed from a captured HIP graph. */
 sgn_status sgn_step(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double t0);
 
+/* Capture and instantiate the HIP graphs that sgn_step(ctx, q, dt, nsteps, .)
+ * replays (one for 8-step runs, one for the 1- or 2-step remainder), so that a
+ * later sgn_step with the same q, dt and path pays no capture; enqueues no
+ * work and leaves q untouched.  Same argument rules as sgn_step; a no-op with
+ * a source term (those steps are launched directly) or nsteps == 0.  Graphs are
+ * dropped by sgn_set_option, sgn_set_stream and sgn_set_bathymetry. */
+sgn_status sgn_prepare_step(sgn_ctx* ctx, void* q, double dt, int64_t nsteps);
+
 /* Relaxation RK4 (fully discrete energy conservation; the extension the paper
  * names in its conclusions).  Each step takes the classical RK4 update
  * d = q_RK4 - q_n (computed on the context's step path into the context's
@@ -166,6 +174,51 @@ sgn_status sgn_step_relaxation(sgn_ctx* ctx, void* q, double dt, int64_t nsteps,
  * (SGN_E_UNSUPPORTED). */
 sgn_status sgn_step_totals(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* series);
 
+/* Result of sgn_step_adaptive (host struct filled by the call). */
+typedef struct {
+  double t;             /* time reached: t_end unless the attempt limit stopped the run */
+  double h_next;        /* the step the controller proposes next */
+  double last_err;      /* error norm of the last attempt */
+  int64_t attempts;     /* accepted + rejected */
+  int64_t accepted;
+  int64_t rejected;
+  int32_t reached_end;  /* 1 when t == t_end */
+} sgn_adaptive_result;
+
+/* Adaptive time integration with the kind of method the paper uses (Section
+ * "Numerical Experiments": an explicit third-order, five-stage Runge-Kutta
+ * method with the first-same-as-last property and an embedded error estimate
+ * driving the step; the paper runs it at rtol = atol = 1e-6).  The paper cites
+ * the method without its coefficients; this pair has that shape:
+ *   Y_{i+1} = y_n + h c_{i+1} k_i, c = (0, 1/3, 3/4, 4/5, 3071/3720),
+ *   y_{n+1} = y_n + h sum b_i k_i, b = (7200668/46553289, 1701/5053,
+ *   6098/15159, 350/5053, 18600/500573): order 3, stability polynomial
+ *   1 + z + z^2/2 + z^3/6 + z^4/31 + z^5/163;
+ *   error estimate e = h b_5 (k_5 - (1 - c_5) k_1 - c_5 k_6), k_6 = f(y_{n+1})
+ *   the next step's k_1 (an embedded second-order method);
+ *   err = RMS over all 5N values of e / (atol + rtol max(|y_n|, |y_{n+1}|)),
+ *   accepted when err <= 1; PI control h_new = h 0.9 err^(-0.7/3)
+ *   errp^(0.4/3) within [0.2, 5] h ([0.2, 1] h after a rejection, errp the last
+ *   accepted err, at least 1e-4), rejected steps retried with
+ *   h max(0.2, 0.9 err^(-1/3)); the last step ends exactly at t_end.
+ * Advances q (device state, context dtype) in place from t0 to t_end with a
+ * first attempted step dt0.  adaptive = 0: fixed steps dt0, all accepted (the
+ * estimate is still formed and recorded).  At most max_attempts attempts (then
+ * out->reached_end = 0).  record (device, may be NULL when record_cap = 0):
+ * (h, err, accepted) of attempt n at record[3n .. 3n+2] for n < record_cap.
+ * Error norms and the controller run on the device (FP64 whatever the dtype);
+ * attempts are replayed from a captured graph and the host looks at the run
+ * state once every 32 attempts.  Uses four more state-sized buffers, allocated
+ * on first use and kept by the context.  Synchronizes.  Errors: SGN_E_ARG
+ * (t_end < t0, dt0 <= 0, negative or zero tolerances, max_attempts < 1),
+ * SGN_E_UNSUPPORTED with a source term, SGN_E_NONFINITE when an error norm is
+ * not finite, SGN_E_NONPOS_DEPTH when an accepted step leaves h <= 0 (q then
+ * holds the last accepted state; out is filled in every case after the
+ * arguments are checked). */
+sgn_status sgn_step_adaptive(sgn_ctx* ctx, void* q, double t0, double t_end, double dt0, double rtol, double atol,
+                             int32_t adaptive, int64_t max_attempts, double* record, int64_t record_cap,
+                             sgn_adaptive_result* out);
+
 /* Total mass 1^T M h (FP64 result, compensated deterministic summation). */
 sgn_status sgn_mass(sgn_ctx* ctx, const void* q, double* out);
 
@@ -184,11 +237,14 @@ sgn_status sgn_rates(sgn_ctx* ctx, const void* q, double* mass_rate, double* ene
 sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
 
 /* Measurement: advance q by nsteps RK4 steps like sgn_step but with direct
- * launches, recording HIP events on the context's stream around every kernel.
- * Four-stage path: ms[s] = mean duration of stage kernel s (0 = first, 1 and 2
- * = middle, 3 = last).  Pair path: ms[0] = pair 1, ms[1] = pair 2, ms[2] =
- * ms[3] = 0.  Fused path: ms[0] = the step kernel, ms[1..3] = 0.  On the pair
- * and fused paths an odd nsteps is rounded up.  Milliseconds; synchronizes. */
+ * launches, recording a HIP event on the context's stream between consecutive
+ * kernels (all enqueued before the first wait, so the kernels run back to
+ * back).  Four-stage path: ms[s] = mean duration of stage kernel s (0 = first,
+ * 1 and 2 = middle, 3 = last).  Pair path: ms[0] = pair 1, ms[1] = pair 2,
+ * ms[2] = ms[3] = 0.  Fused path: ms[0] = the step kernel, ms[1..3] = 0.  On
+ * the pair and fused paths an odd nsteps is rounded up; the means leave out
+ * the first step (two on those paths) when there are more.  nsteps <= 1024
+ * (SGN_E_ARG otherwise).  Milliseconds; synchronizes. */
 sgn_status sgn_profile_stages(sgn_ctx* ctx, void* q, double dt, int64_t nsteps, double* ms);
 
 /* Synchronize and report (then clear) the device health flag. */

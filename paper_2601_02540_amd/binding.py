@@ -30,6 +30,12 @@ class SgnError(RuntimeError):
         self.status = status
 
 
+class SgnAdaptiveResult(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("h_next", ctypes.c_double), ("last_err", ctypes.c_double),
+                ("attempts", ctypes.c_int64), ("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("reached_end", ctypes.c_int32)]
+
+
 class SgnParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("xmin", ctypes.c_double), ("xmax", ctypes.c_double),
@@ -68,6 +74,9 @@ def load_library() -> ctypes.CDLL:
         "sgn_init_aux": ([vp, vp], st),
         "sgn_rhs": ([vp, cvp, vp, d], st),
         "sgn_step": ([vp, vp, d, ctypes.c_int64, d], st),
+        "sgn_prepare_step": ([vp, vp, d, ctypes.c_int64], st),
+        "sgn_step_adaptive": ([vp, vp, d, d, d, d, d, ctypes.c_int32, ctypes.c_int64, dp, ctypes.c_int64,
+                               ctypes.POINTER(SgnAdaptiveResult)], st),
         "sgn_mass": ([vp, cvp, dp], st),
         "sgn_energy": ([vp, cvp, dp], st),
         "sgn_mass_energy": ([vp, cvp, dp, dp], st),
@@ -217,6 +226,29 @@ class Solver:
     def step(self, q, dt: float, nsteps: int = 1, t0: float = 0.0):
         self._chk(self.lib.sgn_step(self.ctx, self._state(q), float(dt), int(nsteps), float(t0)))
         return q
+
+    def prepare_step(self, q, dt: float, nsteps: int):
+        """Instantiate the graphs step(q, dt, nsteps) replays; runs nothing."""
+        self._chk(self.lib.sgn_prepare_step(self.ctx, self._state(q), float(dt), int(nsteps)))
+
+    def step_adaptive(self, q, t0: float, t_end: float, dt0: float, rtol: float = 1e-6, atol: float = 1e-6,
+                      adaptive: bool = True, max_attempts: int = 1_000_000, record: int = 0):
+        """The adaptive five-stage third-order FSAL pair from t0 to t_end, q in
+        place.  Returns a dict of the run (t, h_next, last_err, attempts,
+        accepted, rejected, reached_end) and, with record > 0, a (record, 3)
+        float64 device tensor of (h, err, accepted) per attempt."""
+        torch = _torch()
+        rec = None
+        rp = None
+        if record > 0:
+            rec = torch.full((int(record), 3), float("nan"), dtype=torch.float64, device=self.device)
+            rp = ctypes.cast(ctypes.c_void_p(rec.data_ptr()), ctypes.POINTER(ctypes.c_double))
+        out = SgnAdaptiveResult()
+        self._chk(self.lib.sgn_step_adaptive(self.ctx, self._state(q), float(t0), float(t_end), float(dt0),
+                                             float(rtol), float(atol), 1 if adaptive else 0, int(max_attempts), rp,
+                                             int(record), ctypes.byref(out)))
+        res = {k: getattr(out, k) for k, _ in SgnAdaptiveResult._fields_}
+        return (res, rec) if record > 0 else res
 
     def step_relaxation(self, q, dt: float, nsteps: int = 1, t0: float = 0.0) -> float:
         """Relaxation RK4 steps in place; returns the final time t0 + sum gam_n dt."""

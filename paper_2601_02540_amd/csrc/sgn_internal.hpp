@@ -36,6 +36,21 @@ struct AdjointBuffers {
   double* loss = nullptr;    // device accumulator
 };
 
+// Buffers of the adaptive pair (sgn_step_adaptive), allocated on first use.
+struct FsalBuffers {
+  void* k[2] = {nullptr, nullptr};  // k_1 of the current step / of the next one (FSAL)
+  void* ya = nullptr;               // stage states (ping-pong)
+  void* yb = nullptr;
+  void* e = nullptr;                // partial error estimate
+  double* part = nullptr;           // per-tile sums of the scaled squares
+  size_t part_cap = 0;              // doubles in part
+  void* ctl = nullptr;              // run state (sgn::AdaptCtl) in device memory
+  void* host_ctl = nullptr;         // pinned copy read by the host
+  GraphCache graph;                 // attempts captured for replay
+  double* graph_rec = nullptr;      // record pointer and capacity captured in the graph
+  long long graph_rec_cap = 0;
+};
+
 }  // namespace sgn_host
 
 struct sgn_ctx {
@@ -67,6 +82,7 @@ struct sgn_ctx {
   sgn_host::GraphCache totals_graph;  // steps with recorded totals (sgn_step_totals)
   double* totals_series = nullptr;    // the series pointer captured in totals_graph
   sgn_host::AdjointBuffers adj;
+  sgn_host::FsalBuffers fs;
   std::string err;
 };
 
@@ -77,6 +93,7 @@ sgn_status hip_fail(sgn_ctx* c, hipError_t e, const char* what);
 sgn_status sync_results(sgn_ctx* c, int nres);
 sgn_status check_ctx(sgn_ctx* c, bool need_b);
 void free_adjoint(sgn_ctx* c);
+void free_fsal(sgn_ctx* c);
 // stage kernel of the four-stage path in mode `mode` (sgn::MODE_*)
 hipError_t launch_stage_mode(const sgn_ctx* c, hipStream_t s, int mode, const void* Y, const void* qn, void* acc,
                              void* out, double c_acc, double c_y, double t);
@@ -95,6 +112,10 @@ int step_tiles(const sgn_ctx* c);
 // Makes c->tile_partials hold the epilogue sums of either tile shape
 // (synchronizes and drops the graphs that captured an older buffer).
 sgn_status ensure_tile_partials(sgn_ctx* c);
+// Validation of sgn_params (the rules of sgn_create; failures leave their
+// message for sgn_last_error(NULL)) and the grid constants the kernels take.
+sgn_status check_params(const sgn_params* p);
+sgn::GridConst grid_const(const sgn_params& p);
 
 }  // namespace sgn_host
 

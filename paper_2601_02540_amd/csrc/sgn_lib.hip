@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "sgn.h"
 #include "sgn_internal.hpp"
@@ -62,6 +63,8 @@ void destroy_graphs(sgn_ctx* c) {
   if (c->totals_graph.exec) (void)hipGraphExecDestroy(c->totals_graph.exec);
   c->totals_graph = GraphCache{};
   c->totals_series = nullptr;
+  if (c->fs.graph.exec) (void)hipGraphExecDestroy(c->fs.graph.exec);
+  c->fs.graph = GraphCache{};
 }
 
 int reduce_blocks(const sgn_ctx* c) { return c->p.ny < sgn::RED_MAX_BLOCKS ? c->p.ny : sgn::RED_MAX_BLOCKS; }
@@ -372,6 +375,42 @@ hipError_t enqueue_pair_step(const sgn_ctx* c, hipStream_t s, void* cur, void* o
   return ::enqueue_pair_step(c, s, cur, oth, dt, t);
 }
 
+sgn_status check_params(const sgn_params* p) {
+  if (!p) return fail(nullptr, SGN_E_ARG, "params is NULL");
+  if (p->nx < 4 || p->ny < 4) return fail(nullptr, SGN_E_SHAPE, "each axis needs at least 4 nodes");
+  if (!(std::isfinite(p->xmin) && std::isfinite(p->xmax) && p->xmax > p->xmin && std::isfinite(p->ymin) &&
+        std::isfinite(p->ymax) && p->ymax > p->ymin))
+    return fail(nullptr, SGN_E_SHAPE, "domain bounds must be finite with max > min");
+  if ((p->bc_x != SGN_PERIODIC && p->bc_x != SGN_REFLECTING) || (p->bc_y != SGN_PERIODIC && p->bc_y != SGN_REFLECTING))
+    return fail(nullptr, SGN_E_ARG, "unknown boundary type");
+  if (!(std::isfinite(p->g) && p->g > 0.0)) return fail(nullptr, SGN_E_ARG, "g must be finite and > 0");
+  if (!(std::isfinite(p->lambda) && p->lambda >= 0.0)) return fail(nullptr, SGN_E_ARG, "lambda must be finite and >= 0");
+  if (p->dtype != SGN_F64 && p->dtype != SGN_F32) return fail(nullptr, SGN_E_ARG, "unknown dtype");
+  if (p->source != SGN_SRC_NONE && p->source != SGN_SRC_MMS) return fail(nullptr, SGN_E_ARG, "unknown source");
+  const size_t N = (size_t)p->nx * (size_t)p->ny;
+  if (N > ((size_t)1 << 40)) return fail(nullptr, SGN_E_SHAPE, "grid too large");
+  return SGN_OK;
+}
+
+sgn::GridConst grid_const(const sgn_params& p) {
+  sgn::GridConst gc{};
+  gc.nx = p.nx;
+  gc.ny = p.ny;
+  gc.bc_x = p.bc_x;
+  gc.bc_y = p.bc_y;
+  gc.dx = axis_spacing(p.nx, p.xmin, p.xmax, p.bc_x);
+  gc.dy = axis_spacing(p.ny, p.ymin, p.ymax, p.bc_y);
+  gc.inv2dx = 1.0 / (2.0 * gc.dx);
+  gc.inv2dy = 1.0 / (2.0 * gc.dy);
+  gc.invdx = 1.0 / gc.dx;
+  gc.invdy = 1.0 / gc.dy;
+  gc.xmin = p.xmin;
+  gc.ymin = p.ymin;
+  gc.g = p.g;
+  gc.lam = p.lambda;
+  return gc;
+}
+
 }  // namespace sgn_host
 
 namespace {
@@ -417,19 +456,9 @@ const char* sgn_last_error(const sgn_ctx* c) { return c ? c->err.c_str() : g_cre
 sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
   if (!out) return fail(nullptr, SGN_E_ARG, "out is NULL");
   *out = nullptr;
-  if (!p) return fail(nullptr, SGN_E_ARG, "params is NULL");
-  if (p->nx < 4 || p->ny < 4) return fail(nullptr, SGN_E_SHAPE, "each axis needs at least 4 nodes");
-  if (!(std::isfinite(p->xmin) && std::isfinite(p->xmax) && p->xmax > p->xmin && std::isfinite(p->ymin) &&
-        std::isfinite(p->ymax) && p->ymax > p->ymin))
-    return fail(nullptr, SGN_E_SHAPE, "domain bounds must be finite with max > min");
-  if ((p->bc_x != SGN_PERIODIC && p->bc_x != SGN_REFLECTING) || (p->bc_y != SGN_PERIODIC && p->bc_y != SGN_REFLECTING))
-    return fail(nullptr, SGN_E_ARG, "unknown boundary type");
-  if (!(std::isfinite(p->g) && p->g > 0.0)) return fail(nullptr, SGN_E_ARG, "g must be finite and > 0");
-  if (!(std::isfinite(p->lambda) && p->lambda >= 0.0)) return fail(nullptr, SGN_E_ARG, "lambda must be finite and >= 0");
-  if (p->dtype != SGN_F64 && p->dtype != SGN_F32) return fail(nullptr, SGN_E_ARG, "unknown dtype");
-  if (p->source != SGN_SRC_NONE && p->source != SGN_SRC_MMS) return fail(nullptr, SGN_E_ARG, "unknown source");
+  sgn_status pst = sgn_host::check_params(p);
+  if (pst) return pst;
   const size_t N = (size_t)p->nx * (size_t)p->ny;
-  if (N > ((size_t)1 << 40)) return fail(nullptr, SGN_E_SHAPE, "grid too large");
 
   sgn_ctx* c = new sgn_ctx();
   c->p = *p;
@@ -443,21 +472,7 @@ sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
     delete c;
     return hip_fail(nullptr, e, "hipGetDevice");
   }
-  sgn::GridConst& gc = c->gc;
-  gc.nx = p->nx;
-  gc.ny = p->ny;
-  gc.bc_x = p->bc_x;
-  gc.bc_y = p->bc_y;
-  gc.dx = axis_spacing(p->nx, p->xmin, p->xmax, p->bc_x);
-  gc.dy = axis_spacing(p->ny, p->ymin, p->ymax, p->bc_y);
-  gc.inv2dx = 1.0 / (2.0 * gc.dx);
-  gc.inv2dy = 1.0 / (2.0 * gc.dy);
-  gc.invdx = 1.0 / gc.dx;
-  gc.invdy = 1.0 / gc.dy;
-  gc.xmin = p->xmin;
-  gc.ymin = p->ymin;
-  gc.g = p->g;
-  gc.lam = p->lambda;
+  c->gc = sgn_host::grid_const(*p);
 
   const size_t plane = N * c->esize;
   bool ok = hipMalloc(&c->b, plane) == hipSuccess && hipMalloc(&c->acc, 5 * plane) == hipSuccess &&
@@ -487,6 +502,7 @@ sgn_status sgn_destroy(sgn_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   destroy_graphs(c);
   sgn_host::free_adjoint(c);
+  sgn_host::free_fsal(c);
   if (c->b) (void)hipFree(c->b);
   if (c->acc) (void)hipFree(c->acc);
   if (c->ya) (void)hipFree(c->ya);
@@ -581,6 +597,21 @@ sgn_status sgn_step(sgn_ctx* c, void* q, double dt, int64_t nsteps, double t0) {
   return SGN_OK;
 }
 
+sgn_status sgn_prepare_step(sgn_ctx* c, void* q, double dt, int64_t nsteps) {
+  sgn_status st = check_ctx(c, true);
+  if (st) return st;
+  if (!q) return fail(c, SGN_E_ARG, "q is NULL");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, SGN_E_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(c, SGN_E_ARG, "nsteps must be >= 0");
+  if (nsteps == 0 || c->p.source != SGN_SRC_NONE) return SGN_OK;
+  // the same split as sgn_step: 8-step replays, then 1- or 2-step replays
+  hipGraphExec_t ge;
+  if (nsteps >= GRAPH_STEPS && (st = get_graph(c, 0, q, dt, GRAPH_STEPS, &ge))) return st;
+  const int small = double_steps(c) ? 2 : 1;
+  if (nsteps % GRAPH_STEPS >= small && (st = get_graph(c, 1, q, dt, small, &ge))) return st;
+  return SGN_OK;
+}
+
 sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
   if (!c) return SGN_E_ARG;
   if (option == SGN_OPT_STEP_PATH) {
@@ -660,64 +691,75 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if (st) return st;
   if (!q || !ms) return fail(c, SGN_E_ARG, "q or ms is NULL");
   if (!(std::isfinite(dt) && dt > 0.0) || nsteps <= 0) return fail(c, SGN_E_ARG, "dt must be > 0 and nsteps > 0");
+  if (nsteps > 1024) return fail(c, SGN_E_ARG, "nsteps must be <= 1024");
   const bool pairs = c->step_path == SGN_PATH_PAIRS;
   const bool fused = c->step_path == SGN_PATH_FUSED;
   if ((pairs || fused) && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
   const int nk = fused ? 2 : 4;                      // launches recorded per profiled unit
-  hipEvent_t ev[5];
-  for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventCreate(&ev[k]));
-  double acc_ms[4] = {0, 0, 0, 0};
-  hipError_t e = hipSuccess;
   const int64_t units = (pairs || fused) ? nsteps / 2 : nsteps;
+  // One event between consecutive launches, all enqueued before the first
+  // wait, so the kernels run back to back as in a timed run; with more than
+  // one unit the first (warm-up) unit is left out of the means.
+  std::vector<hipEvent_t> ev((size_t)(units * nk + 1), nullptr);
+  hipError_t e = hipSuccess;
+  for (auto& x : ev)
+    if (!e) e = hipEventCreate(&x);
+  int n = 0;
+  if (!e) e = hipEventRecord(ev[n++], c->stream);
   for (int64_t u = 0; u < units && e == hipSuccess; ++u) {
     const double t = (double)u * ((pairs || fused) ? 2.0 : 1.0) * dt;
-    e = hipEventRecord(ev[0], c->stream);
     if (fused) {
       // two consecutive steps (q -> acc -> q)
-      if (!e) e = launch_fused(c, c->stream, q, c->acc, dt, t);
-      if (!e) e = hipEventRecord(ev[1], c->stream);
+      e = launch_fused(c, c->stream, q, c->acc, dt, t);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_fused(c, c->stream, c->acc, q, dt, t + dt);
-      if (!e) e = hipEventRecord(ev[2], c->stream);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
     } else if (pairs) {
       // pair 1 and pair 2 of two consecutive steps (q -> acc -> q)
-      if (!e) e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
-      if (!e) e = hipEventRecord(ev[1], c->stream);
+      e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_pair<2>(c, c->stream, c->yb, q, c->acc, nullptr, dt / 3.0, dt, dt / 6.0, 0.0, t + dt / 2.0, t + dt);
-      if (!e) e = hipEventRecord(ev[2], c->stream);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_pair<1>(c, c->stream, c->acc, nullptr, q, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t + dt, t + 1.5 * dt);
-      if (!e) e = hipEventRecord(ev[3], c->stream);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_pair<2>(c, c->stream, c->yb, c->acc, q, nullptr, dt / 3.0, dt, dt / 6.0, 0.0, t + 1.5 * dt, t + 2.0 * dt);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
     } else {
-      if (!e) e = launch_stage<sgn::MODE_FIRST>(c, c->stream, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t);
-      if (!e) e = hipEventRecord(ev[1], c->stream);
+      e = launch_stage<sgn::MODE_FIRST>(c, c->stream, q, nullptr, c->acc, c->ya, dt / 6.0, dt / 2.0, t);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->ya, q, c->acc, c->yb, dt / 3.0, dt / 2.0, t + dt / 2.0);
-      if (!e) e = hipEventRecord(ev[2], c->stream);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_stage<sgn::MODE_MID>(c, c->stream, c->yb, q, c->acc, c->ya, dt / 3.0, dt, t + dt / 2.0);
-      if (!e) e = hipEventRecord(ev[3], c->stream);
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_stage<sgn::MODE_LAST>(c, c->stream, c->ya, nullptr, c->acc, q, dt / 6.0, 0.0, t + dt);
-    }
-    if (!e) e = hipEventRecord(ev[nk], c->stream);
-    if (!e) e = hipEventSynchronize(ev[nk]);
-    for (int k = 0; k < nk && !e; ++k) {
-      float m = 0.f;
-      e = hipEventElapsedTime(&m, ev[k], ev[k + 1]);
-      acc_ms[k] += m;
+      if (!e) e = hipEventRecord(ev[n++], c->stream);
     }
   }
-  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+  if (!e) e = hipEventSynchronize(ev[n - 1]);
+  double acc_ms[4] = {0, 0, 0, 0};
+  const int64_t first = units > 1 ? 1 : 0;
+  for (int64_t u = first; u < units && !e; ++u)
+    for (int k = 0; k < nk && !e; ++k) {
+      float m = 0.f;
+      e = hipEventElapsedTime(&m, ev[(size_t)(u * nk + k)], ev[(size_t)(u * nk + k + 1)]);
+      acc_ms[k] += m;
+    }
+  for (auto& x : ev)
+    if (x) (void)hipEventDestroy(x);
   if (e != hipSuccess) return hip_fail(c, e, "profiled step");
+  const double used = (double)(units - first);
   if (fused) {
     // ms[0] = one fused step (mean over both steps of each unit)
-    ms[0] = (acc_ms[0] + acc_ms[1]) / (2.0 * (double)units);
+    ms[0] = (acc_ms[0] + acc_ms[1]) / (2.0 * used);
     ms[1] = ms[2] = ms[3] = 0.0;
   } else if (pairs) {
     // ms[0] = pair 1, ms[1] = pair 2 (means over both steps of each unit)
-    ms[0] = (acc_ms[0] + acc_ms[2]) / (2.0 * (double)units);
-    ms[1] = (acc_ms[1] + acc_ms[3]) / (2.0 * (double)units);
+    ms[0] = (acc_ms[0] + acc_ms[2]) / (2.0 * used);
+    ms[1] = (acc_ms[1] + acc_ms[3]) / (2.0 * used);
     ms[2] = 0.0;
     ms[3] = 0.0;
   } else {
-    for (int k = 0; k < 4; ++k) ms[k] = acc_ms[k] / (double)units;
+    for (int k = 0; k < 4; ++k) ms[k] = acc_ms[k] / used;
   }
   return sync_results(c, 0);
 }

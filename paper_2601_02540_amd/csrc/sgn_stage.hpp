@@ -97,7 +97,9 @@ __device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Nod
   const T xphu = xp.h * xp.u, xmhu = xm.h * xm.u;
   const T dxhu = xphu - xmhu;
   const T dxhuv = xphu * xp.v - xmhu * xm.v;
-  const T dxe2h = xp.eta * xp.eta * xp.ih - xm.eta * xm.eta * xm.ih;
+  // D(eta^2/h) = D(h) + D((eta - h)(eta + h)/h): the second part is small
+  // (eta stays close to h), so it is formed without cancellation
+  const T dxe2c = (xp.eta - xp.h) * (xp.eta + xp.h) * xp.ih - (xm.eta - xm.h) * (xm.eta + xm.h) * xm.ih;
   const T dxhuw = xphu * xp.w - xmhu * xm.w;
   // y differences (12), unscaled
   const T dyh = yp.h - ym.h;
@@ -111,13 +113,16 @@ __device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Nod
   const T yphv = yp.h * yp.v, ymhv = ym.h * ym.v;
   const T dyhv = yphv - ymhv;
   const T dyhuv = yphv * yp.u - ymhv * ym.u;
-  const T dye2h = yp.eta * yp.eta * yp.ih - ym.eta * ym.eta * ym.ih;
+  const T dye2c = (yp.eta - yp.h) * (yp.eta + yp.h) * yp.ih - (ym.eta - ym.h) * (ym.eta + ym.h) * ym.ih;
   const T dyhvw = yphv * yp.w - ymhv * ym.w;
 
   const T h = c.h, u = c.u, v = c.v, w = c.w, eta = c.eta;
   const T H = h + c.b;
-  const T r = eta * c.ih;
-  const T omr = T(1) - r;
+  // r - 1 = (eta - h)/h and r^2 - 1 = (r - 1)(r + 1), formed from eta - h, so
+  // that a state at rest (eta = h) gives exactly zero relaxation terms
+  const T rm1 = (eta - h) * c.ih;
+  const T omr = -rm1;
+  const T r2m1 = rm1 * (rm1 + T(2));
   const T hu = h * u, hv = h * v, uv = u * v, hw = h * w;
   const T lam6 = lam * T(1.0 / 6.0), lam3 = lam * T(1.0 / 3.0), lam2 = lam * T(0.5);
   const T hsx = half * sx, hsy = half * sy;
@@ -128,11 +133,12 @@ __device__ __forceinline__ Rates<T> split_form_rates(const Node<T>& c, const Nod
   if (BCY == BC_REFLECTING) k.h += saty_coef * hv;
 
   // A = h u_t, B = h v_t (with the sign of the rates), C = the flux part of h w_t
-  const T Ax = g * (dxhH - H * dxh) + lam6 * (r * r * dxh - dxe2h) + lam3 * omr * dxeta + lam2 * omr * dxb;
+  // lambda/6 (r^2 D h - D(eta^2/h)) = lambda/6 ((r^2 - 1) D h - D((eta - h)(eta + h)/h))
+  const T Ax = g * (dxhH - H * dxh) + lam6 * (r2m1 * dxh - dxe2c) + lam3 * omr * dxeta + lam2 * omr * dxb;
   const T Ax2 = h * dxu2 - u * u * dxh + u * dxhu - hu * dxu;
   const T Ay2 = dyhuv - uv * dyh + hv * dyu - hu * dyv;
   const T A = sx * Ax + hsx * Ax2 + hsy * Ay2;
-  const T By = g * (dyhH - H * dyh) + lam6 * (r * r * dyh - dye2h) + lam3 * omr * dyeta + lam2 * omr * dyb;
+  const T By = g * (dyhH - H * dyh) + lam6 * (r2m1 * dyh - dye2c) + lam3 * omr * dyeta + lam2 * omr * dyb;
   const T By2 = h * dyv2 - v * v * dyh + v * dyhv - hv * dyv;
   const T Bx2 = dxhuv - uv * dxh + hu * dxv - hv * dxu;
   const T B = sy * By + hsy * By2 + hsx * Bx2;

@@ -10,6 +10,18 @@ import numpy as np
 STATE_FLOORS = (1.0, math.sqrt(9.81), math.sqrt(9.81), math.sqrt(9.81), 1.0)
 
 
+# FP32 results are bounded by four times the error of the oracle evaluated in
+# single precision, both measured field-relative against the FP64 oracle.
+# Where the oracle's FP32 error is smaller than the rounding of the field
+# itself to FP32 (a field that barely moves), the bound uses that rounding
+# instead: half an FP32 ulp of the field scale, 2^-24.
+FP32_FLOOR = 2.0 ** -24
+
+
+def fp32_bound(oracle_f32_err):
+    return 4.0 * np.maximum(oracle_f32_err, FP32_FLOOR)
+
+
 def dev(a, dtype=None):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(a))
@@ -92,6 +104,6 @@ def check_windows(grid, q0, b, got, dt, steps, windows, win=32, f32=False):
         if f32:
             o32 = oracle.rk4_f32(wg, qw, bw, dt, steps).astype(np.float64)[:, keep_y, keep_x]
             bound = field_rel_err(o32, ref, STATE_FLOORS)
-            assert np.all(err <= 4 * bound + 1e-6), ((ky, sy), (kx, sx), err, bound)
+            assert np.all(err <= fp32_bound(bound)), ((ky, sy), (kx, sx), err, bound)
         else:
             assert np.all(err <= 1e-12), ((ky, sy), (kx, sx), err)

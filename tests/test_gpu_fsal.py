@@ -1,0 +1,142 @@
+"""GPU parity of the adaptive five-stage FSAL pair (sgn_step_adaptive) against
+the oracle's pair (oracle.fsal35), through the C ABI.
+
+Both sides initialize the workload themselves and take their own CFL step as
+the first attempted step; each records (h, err, accepted) per attempt.  The
+attempt sequences must agree: the same accept/reject decisions, steps and error
+norms within 1e-10 relative (they differ only by rounding, which the
+controller's powers pass on), and the final state within 1e-12 field-relative
+(FP64).  Fixed-step runs (every step accepted) are compared the same way, on
+both boundary types and both tile heights, and FP32 runs against the FP32
+bound of the plain step."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2601_02540_amd import workloads as W
+from gpu_util import STATE_FLOORS, dev, field_rel_err, fp32_bound, host, solver
+
+pytestmark = pytest.mark.gpu
+
+PER, REF = W.PERIODIC, W.REFLECTING
+F64_TOL = 1e-12
+
+
+def compare_records(got, ref):
+    """Same decisions; steps within 1e-10 relative; error norms within 1e-10
+    relative plus 1e-12 absolute: a small norm is a difference of nearly equal
+    rates, whose rounding (~1e-16 |h k| / tol, about 1e-13 on the final, cut
+    step of these runs) stays far below the threshold 1 it is compared with."""
+    assert got.shape == ref.shape, (got.shape, ref.shape)
+    assert np.array_equal(got[:, 2], ref[:, 2])
+    np.testing.assert_allclose(got[:, 0], ref[:, 0], rtol=1e-10, atol=0)
+    np.testing.assert_allclose(got[:, 1], ref[:, 1], rtol=1e-10, atol=1e-12)
+
+
+def run_gpu(g, q0, b, t_end, dt0, dtype=torch.float64, ty=None, **kw):
+    s = solver(g, dtype)
+    if ty is not None:
+        s.set_tile_y(ty)
+    s.set_bathymetry(dev(b, dtype))
+    qd = dev(q0, dtype)
+    res, rec = s.step_adaptive(qd, 0.0, t_end, dt0, record=4096, **kw)
+    n = res["attempts"]
+    rec = host(rec)[:n]
+    return res, rec, host(qd)
+
+
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_adaptive_run_matches_oracle(bc):
+    """rtol = atol = 1e-6 (the paper's tolerances) on a 64^2 Gaussian bump
+    (periodic, lambda = 500) and on a wavy reflecting state."""
+    if bc == PER:
+        p = W.gaussian_bump_periodic(64, seed=1)
+        g, b = p.grid, p.b
+        q0 = oracle.init_aux(g, p.q0, b)
+        t_end = 1.0
+    else:
+        g = W.Grid(96, 40, 0.0, 30.0, 0.0, 10.0, REF, REF, 9.81, 500.0)
+        q, b = W.random_state(g, 11, b_scale=0.05)
+        q[1:4] *= 0.05
+        q0 = oracle.init_aux(g, q, b)
+        t_end = 0.2
+    dt0 = oracle.cfl_dt(g, q0, 0.5)
+    ref, t_ref, na, nr, rec_ref = oracle.fsal35(g, q0, b, 0.0, t_end, dt0)
+    res, rec, got = run_gpu(g, q0, b, t_end, dt0)
+    assert res["reached_end"] == 1 and res["t"] == t_ref == t_end
+    assert (res["accepted"], res["rejected"]) == (na, nr)
+    compare_records(rec, rec_ref)
+    err = field_rel_err(got, ref, STATE_FLOORS)
+    assert np.all(err <= F64_TOL), err
+
+
+def test_too_large_first_step_is_rejected_like_the_oracle():
+    p = W.gaussian_bump_periodic(64, seed=2)
+    g, b = p.grid, p.b
+    q0 = oracle.init_aux(g, p.q0, b)
+    dt_cfl = oracle.cfl_dt(g, q0, 0.5)
+    t_end = 30 * dt_cfl
+    ref, t_ref, na, nr, rec_ref = oracle.fsal35(g, q0, b, 0.0, t_end, 15 * dt_cfl)
+    assert nr >= 1
+    res, rec, got = run_gpu(g, q0, b, t_end, 15 * dt_cfl)
+    compare_records(rec, rec_ref)
+    assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
+
+
+@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF)])
+def test_fixed_steps_match_oracle(bcs, ty):
+    """Fixed steps (adaptive = 0) on a ragged grid: the state after 7 steps and
+    the recorded error norms."""
+    g = W.Grid(70, 37, -1.0, 2.0, 0.5, 2.0, bcs[0], bcs[1], 9.81, 500.0)
+    q, b = W.random_state(g, 5, b_scale=0.05)
+    q[1:4] *= 0.1
+    q0 = oracle.init_aux(g, q, b)
+    dt = 0.3 * oracle.cfl_dt(g, q0, 0.5)
+    ref, _, na, _, rec_ref = oracle.fsal35(g, q0, b, 0.0, 7 * dt, dt, adaptive=False)
+    res, rec, got = run_gpu(g, q0, b, 7 * dt, dt, ty=ty, adaptive=False)
+    assert res["accepted"] == na == 7 and res["rejected"] == 0
+    compare_records(rec, rec_ref)
+    assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
+
+
+def test_fp32_bounded_by_oracle_fp32_error():
+    """FP32 storage and arithmetic, fixed steps: within the FP32 bound of the
+    plain RK4 step over the same interval (the pair's rounding is of the same
+    kind), against the FP64 oracle pair."""
+    p = W.gaussian_bump_periodic(64, seed=1)
+    g = p.grid
+    b32 = p.b.astype(np.float32).astype(np.float64)
+    q0 = oracle.init_aux(g, p.q0, b32).astype(np.float32).astype(np.float64)
+    dt = oracle.cfl_dt(g, q0, 0.5)
+    ref, *_ = oracle.fsal35(g, q0, b32, 0.0, 20 * dt, dt, adaptive=False)
+    bound = field_rel_err(oracle.rk4_f32(g, q0, b32, dt, 20).astype(np.float64), oracle.rk4(g, q0, b32, dt, 20),
+                          STATE_FLOORS)
+    res, rec, got = run_gpu(g, q0, b32, 20 * dt, dt, dtype=torch.float32, adaptive=False)
+    assert res["accepted"] == 20
+    err = field_rel_err(got, ref, STATE_FLOORS)
+    assert np.all(err <= fp32_bound(bound)), (err, bound)
+
+
+def test_attempt_limit_and_arguments():
+    from paper_2601_02540_amd.binding import SgnError
+    p = W.gaussian_bump_periodic(32, seed=3)
+    g = p.grid
+    s = solver(g)
+    s.set_bathymetry(dev(p.b))
+    qd = dev(oracle.init_aux(g, p.q0, p.b))
+    dt = s.cfl_dt(qd, 0.5)
+    res = s.step_adaptive(qd, 0.0, 100 * dt, dt, max_attempts=5)
+    assert res["reached_end"] == 0 and res["attempts"] == 5 and res["t"] < 100 * dt
+    for bad in (dict(t0=1.0, t_end=0.0, dt0=dt), dict(t0=0.0, t_end=1.0, dt0=0.0),
+                dict(t0=0.0, t_end=1.0, dt0=dt, rtol=0.0, atol=0.0), dict(t0=0.0, t_end=1.0, dt0=dt, max_attempts=0)):
+        with pytest.raises(SgnError) as ei:
+            s.step_adaptive(qd, **bad)
+        assert ei.value.status == -1
+    src = solver(W.mms_grid(32, PER), source=1)
+    src.set_bathymetry(dev(np.zeros((32, 32))))
+    with pytest.raises(SgnError) as ei:
+        src.step_adaptive(dev(np.ones((5, 32, 32))), 0.0, 1.0, 1e-3)
+    assert ei.value.status == -3
