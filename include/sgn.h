@@ -229,6 +229,24 @@ sgn_status sgn_energy(sgn_ctx* ctx, const void* q, double* out);
 /* Both totals in one pass. */
 sgn_status sgn_mass_energy(sgn_ctx* ctx, const void* q, double* mass, double* energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the totals of
+ * sgn_mass_energy without a context.  Same kernels, so the same bits as
+ * sgn_mass_energy on a context with these params and bathymetry.
+ *   params: validated like sgn_create (source ignored); q: device state
+ *   (5 planes, params->dtype); b: device bathymetry plane (params->dtype);
+ *   stream: hipStream_t (NULL for the null stream); out: device memory of two
+ *   doubles, receives mass and energy (FP64 whatever the dtype).
+ * Asynchronous on stream; allocates nothing: the partial sums go to a static
+ * device array of 32 KiB that each GPU holds until the process ends (every grid
+ * size fits), looked up once per device on the first call there.  Calls that
+ * overlap on one GPU (different streams or threads) share that array and race:
+ * order them.  Errors: SGN_E_ARG / SGN_E_SHAPE as sgn_create or for NULL
+ * pointers, SGN_E_HIP for launch failures; the message is left for
+ * sgn_last_error(NULL). */
+sgn_status sgn_mass_energy_noalloc(const sgn_params* params, const void* q, const void* b, void* stream,
+                                   double* out);
+
 /* Semi-discrete rates 1^T M h_t and <d_q E, q_t>_M (Theorem 1 proof); both
  * vanish up to rounding for any state with h > 0.  Uses the context's scratch. */
 sgn_status sgn_rates(sgn_ctx* ctx, const void* q, double* mass_rate, double* energy_rate);

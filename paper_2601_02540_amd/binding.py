@@ -80,6 +80,7 @@ def load_library() -> ctypes.CDLL:
         "sgn_mass": ([vp, cvp, dp], st),
         "sgn_energy": ([vp, cvp, dp], st),
         "sgn_mass_energy": ([vp, cvp, dp, dp], st),
+        "sgn_mass_energy_noalloc": ([ctypes.POINTER(SgnParams), cvp, cvp, vp, dp], st),
         "sgn_rates": ([vp, cvp, dp, dp], st),
         "sgn_cfl_dt": ([vp, cvp, d, dp], st),
         "sgn_check": ([vp], st),
@@ -133,6 +134,33 @@ def _require_gpu():
     torch = _torch()
     if not torch.cuda.is_available():
         raise RuntimeError("the SGN solver runs only on a ROCm GPU (torch.cuda.is_available() is False)")
+
+
+def mass_energy_noalloc(grid, q, b, out, stream=None):
+    """sgn_mass_energy_noalloc: mass and energy of state q (5 planes) over
+    bathymetry b into the device tensor out (2 float64 values), asynchronously
+    on `stream` (default: the current stream), without a context and without
+    any allocation by the library."""
+    torch = _torch()
+    _require_gpu()
+    lib = load_library()
+    if q.dtype not in (torch.float64, torch.float32) or b.dtype != q.dtype:
+        raise ValueError("q and b must share dtype float64 or float32")
+    if tuple(q.shape) != (5, grid.ny, grid.nx) or tuple(b.shape) != (grid.ny, grid.nx):
+        raise ValueError("q must be (5, ny, nx) and b (ny, nx)")
+    if not (q.is_cuda and b.is_cuda and out.is_cuda and q.is_contiguous() and b.is_contiguous()):
+        raise ValueError("q, b and out must be contiguous device tensors")
+    if out.dtype != torch.float64 or out.numel() < 2 or not out.is_contiguous():
+        raise ValueError("out must hold two contiguous float64 values")
+    stream = torch.cuda.current_stream(q.device) if stream is None else stream
+    p = SgnParams(grid.nx, grid.ny, grid.xmin, grid.xmax, grid.ymin, grid.ymax, grid.bc_x, grid.bc_y,
+                  grid.g, grid.lam, SGN_F64 if q.dtype == torch.float64 else SGN_F32, SGN_SRC_NONE)
+    s = lib.sgn_mass_energy_noalloc(ctypes.byref(p), ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                    ctypes.c_void_p(stream.cuda_stream),
+                                    ctypes.cast(ctypes.c_void_p(out.data_ptr()), ctypes.POINTER(ctypes.c_double)))
+    if s != 0:
+        raise SgnError(s, lib.sgn_last_error(None).decode())
+    return out
 
 
 class Solver:

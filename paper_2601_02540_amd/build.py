@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsgn.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("sgn_lib.hip", "sgn_batch.hip", "sgn_adjoint.hip", "sgn_relax.hip",
-                                                "sgn_totals.hip", "sgn_fsal.hip")]
+                                                "sgn_totals.hip", "sgn_noalloc.hip", "sgn_fsal.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in sorted(os.listdir(CSRC)) if f.endswith((".hpp", ".h"))] + [
     os.path.join(INCLUDE, "sgn.h")]
 
