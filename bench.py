@@ -66,10 +66,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
 # they had when the counters were taken.
-STEP_TRAFFIC_BYTES_PER_NODE = (1185575387.4 + 671088640.0) / 16777216
+STEP_TRAFFIC_BYTES_PER_NODE = (1184915927.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "f1a4b1c069e5640ee73d5f1a722a734e73327a2ad367f490d7961637c5d4e094"
+STEP_SOURCES_SHA256 = "77fbc46cfeeaf6dd9665b98784f6478a7a2f6da5f87d337f4ddc0662cff3df1a"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
@@ -147,8 +147,10 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, rep
         t += steps * dt
     sec = float(np.median(secs))
     # per-launch durations of the path's kernels (direct launches with HIP events between them),
-    # right after the timed runs: after an idle spell the GPU's first launches run up to 30% slower
-    ms = s.profile_stages(q, dt, 10)
+    # after an unrecorded pass of 24 steps: the GPU runs the first ~20 launches after an idle spell
+    # up to 30% slower while its clocks settle
+    s.profile_stages(q, dt, 24)
+    ms = s.profile_stages(q, dt, 16)
     s.check()
     m1, e1 = s.mass_energy(q)
     cells = grid.nx * grid.ny
@@ -240,6 +242,14 @@ def run_ensemble(count, steps, warmup, dtype, label, path="fused"):
         "max_abs_energy_drift_rel": max(abs(b - a) / abs(a) for a, b in zip(e0, e1)),
         "max_abs_mass_drift_rel": max(abs(b - a) / abs(a) for a, b in zip(m0, m1)),
     }
+    # two 128^2 instances (one per boundary type) for the comparison with the FP64 oracle
+    picks = {}
+    for bc in (0, 1):
+        i = next((k for k, p in enumerate(probs) if p.grid.bc_x == bc and p.grid.nx == 128), None)
+        if i is not None:
+            picks[f"ensemble_{i}"] = {"instance": i, "steps": warmup + steps, "mass0": m0[i], "energy0": e0[i],
+                                      "mass": m1[i], "energy": e1[i]}
+    res["drift_instances"] = picks
     log(f"[{label}] {res['value']:.4e} node-stage/s over {nodes} nodes  {res['ms_per_step']:.3f} ms/step  "
         f"{achieved:.0f} GB/s  tiles ty={ty} bpc={bpc}")
     batch.close()
@@ -492,6 +502,18 @@ def run_adaptive(nx, t_end, label, rtol=1e-6, atol=1e-6):
     res = s.step_adaptive(q, 0.0, t_end, dt_cfl, rtol, atol)
     wall = time.perf_counter() - t0
     m1, e1 = s.mass_energy(q)
+    # the same run with one role kernel per evaluation (the four-stage path)
+    s.set_step_path("stages")
+    qs = q0.clone()
+    s.step_adaptive(qs, 0.0, 4 * dt_cfl, dt_cfl, rtol, atol)
+    qs.copy_(q0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    res_roles = s.step_adaptive(qs, 0.0, t_end, dt_cfl, rtol, atol)
+    wall_roles = time.perf_counter() - t2
+    same_bits = bool(torch.equal(qs, q)) and res_roles == res
+    s.set_step_path("fused")
+    del qs
     # fixed-step RK4 over the same interval
     n_rk4 = math.ceil(t_end / dt_cfl)
     qr = q0.clone()
@@ -509,13 +531,16 @@ def run_adaptive(nx, t_end, label, rtol=1e-6, atol=1e-6):
            "mean_step": t_end / res["accepted"], "cfl_step": dt_cfl,
            "ms_per_attempt": wall / res["attempts"] * 1e3,
            "rhs_evals_per_s": cells * 5 * res["attempts"] / wall,
+           "role_kernels": {"wall_s": wall_roles, "ms_per_attempt": wall_roles / res_roles["attempts"] * 1e3,
+                            "same_bits": same_bits},
            "mass_drift_rel": (m1 - m0) / abs(m0), "energy_drift_rel": (e1 - e0) / abs(e0),
            "rk4_fixed": {"steps": n_rk4, "wall_s": wall_rk4, "rhs_evals_per_s": cells * 4 * n_rk4 / wall_rk4,
                          "energy_drift_rel": (er - e0) / abs(e0)},
            "max_abs_h_diff_vs_rk4": diff}
     log(f"[{label}] {res['accepted']} accepted / {res['rejected']} rejected steps to t = {t_end} "
         f"(mean step {out['mean_step']:.3e}, CFL step {dt_cfl:.3e}) in {wall:.3f} s; "
-        f"RK4 at the CFL step: {n_rk4} steps in {wall_rk4:.3f} s")
+        f"RK4 at the CFL step: {n_rk4} steps in {wall_rk4:.3f} s; role kernels: {wall_roles:.3f} s "
+        f"(same bits: {same_bits})")
     s.close()
     torch.cuda.empty_cache()
     return out
@@ -573,10 +598,34 @@ def oracle_child(spec):
         entry["drift_steps"] = m
         entry["mass"], entry["energy"] = oracle.mass_energy(g, qm, p.b)
         out["bcs"][name] = entry
+    # smaller runs: the oracle's own totals after the same number of steps
+    out["extra"] = {}
+    for name, steps in spec.get("extra", {}).items():
+        p = extra_problem(name)
+        g = p.grid
+        q = oracle.init_aux(g, p.q0, p.b)
+        dt = oracle.cfl_dt(g, q, 0.5)
+        m0, e0 = oracle.mass_energy(g, q, p.b)
+        with oracle.threaded():
+            qm = oracle.rk4(g, q, p.b, dt, steps)
+        m1, e1 = oracle.mass_energy(g, qm, p.b)
+        out["extra"][name] = {"drift_steps": steps, "mass0": m0, "energy0": e0, "mass": m1, "energy": e1}
     print(json.dumps(out), flush=True)
 
 
-def run_oracle_child(n, bcs, drift_steps, serial_steps):
+def extra_problem(name):
+    """The seeded workloads of the smaller bench runs, by name (each side builds its own)."""
+    from paper_2601_02540_amd import workloads as W
+    if name == "gaussian_bump_64":
+        return W.gaussian_bump_periodic(64, seed=1)
+    if name == "soliton_512":
+        return W.soliton_over_bathymetry(512, seed=2)
+    if name.startswith("ensemble_"):
+        return W.ensemble(256, seed=4)[int(name.split("_")[1])]
+    raise ValueError(name)
+
+
+def run_oracle_child(n, bcs, drift_steps, serial_steps, extra=None):
     """Runs oracle_child in a fresh process.  glibc would return every freed
     plane to the system and fault it in again, page by page and serially, on
     the next call; the child keeps freed memory in its heap instead (malloc
@@ -584,7 +633,7 @@ def run_oracle_child(n, bcs, drift_steps, serial_steps):
     buffers come from."""
     import subprocess
     env = dict(os.environ, MALLOC_MMAP_THRESHOLD_=str(1 << 40), MALLOC_TRIM_THRESHOLD_=str(1 << 42))
-    spec = {"n": n, "bcs": bcs, "drift_steps": drift_steps, "serial_steps": serial_steps}
+    spec = {"n": n, "bcs": bcs, "drift_steps": drift_steps, "serial_steps": serial_steps, "extra": extra or {}}
     r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-child", json.dumps(spec)],
                        env=env, capture_output=True, text=True, check=True)
     return json.loads(r.stdout.strip().splitlines()[-1])
@@ -607,10 +656,10 @@ def cpu_baseline(orc):
     return res
 
 
-def vs_oracle(gpu_res, orc_entry):
+def vs_oracle(gpu_res, orc_entry, d=None):
     """Totals after the same number of steps from each side's own initialization
     of the workload: GPU (any storage type) against the FP64 oracle."""
-    d = gpu_res.get("drift_series")
+    d = gpu_res.get("drift_series") if d is None else d
     if d is None or orc_entry is None or d["steps"] != orc_entry["drift_steps"]:
         return None
     return {"steps": d["steps"],
@@ -740,9 +789,11 @@ def main():
                                                     "pairs" if P == "pairs" else "fused")
     if "small" in chosen:
         small = W.gaussian_bump_periodic(64, seed=1)
-        variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T, R)
+        variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T, R,
+                                                   200 if DS > 0 else 0)
         sol = W.soliton_over_bathymetry(512, seed=2)
-        variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T, R)
+        variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T, R,
+                                                         50 if DS > 0 else 0)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
     if "relaxation" in chosen:
@@ -766,13 +817,27 @@ def main():
         bcs = ["periodic"] + (["reflecting"] if "reflecting_f64" in variants and DS > 0 else [])
         log(f"[bench] FP64 oracle on the same workload ({', '.join(bcs)}): {DS} threaded steps, "
             f"{0 if args.no_cpu_baseline else args.oracle_serial_steps} serial")
-        orc = run_oracle_child(n, bcs, max(DS, 1), 0 if args.no_cpu_baseline else args.oracle_serial_steps)
+        extra = {}
+        if DS > 0:
+            for key, name in (("gaussian_bump_64_f64", "gaussian_bump_64"), ("soliton_512_reflecting_f64", "soliton_512")):
+                if key in variants and "drift_series" in variants[key]:
+                    extra[name] = variants[key]["drift_series"]["steps"]
+            for name, d in variants.get("ensemble_256_f32", {}).get("drift_instances", {}).items():
+                extra[name] = d["steps"]
+        orc = run_oracle_child(n, bcs, max(DS, 1), 0 if args.no_cpu_baseline else args.oracle_serial_steps, extra)
         if not args.no_cpu_baseline:
             cpu = cpu_baseline(orc)
             log(f"[bench] cpu {cpu['value']:.3e} cell-stage/s on {cpu['cores']} threads")
         for name, res in [("periodic", main_res)] + [(k.split("_")[0], v) for k, v in variants.items()
                                                      if k in ("periodic_f32", "reflecting_f64", "reflecting_f32")]:
             res["energy_vs_oracle"] = vs_oracle(res, orc["bcs"].get(name))
+        for key, name in (("gaussian_bump_64_f64", "gaussian_bump_64"), ("soliton_512_reflecting_f64", "soliton_512")):
+            if key in variants:
+                variants[key]["energy_vs_oracle"] = vs_oracle(variants[key], orc.get("extra", {}).get(name))
+        ens = variants.get("ensemble_256_f32")
+        if ens is not None:
+            ens["energy_vs_oracle"] = {name: vs_oracle(ens, orc.get("extra", {}).get(name), dict(d, steps=d["steps"]))
+                                       for name, d in ens.get("drift_instances", {}).items()}
 
     cells = n * n
     line = {

@@ -208,8 +208,12 @@ typedef struct {
  * (h, err, accepted) of attempt n at record[3n .. 3n+2] for n < record_cap.
  * Error norms and the controller run on the device (FP64 whatever the dtype);
  * attempts are replayed from a captured graph and the host looks at the run
- * state once every 32 attempts.  Uses four more state-sized buffers, allocated
- * on first use and kept by the context.  Synchronizes.  Errors: SGN_E_ARG
+ * state once every 32 attempts.  SGN_OPT_STEP_PATH picks the kernels of an
+ * attempt: on SGN_PATH_FUSED (default) the four evaluations after k_1 run in
+ * one launch of the step kernel's tile (the stages stay in LDS), on the other
+ * paths as four stage kernels; the same bits either way.  Uses three more
+ * state-sized buffers (two k_1 and the error estimate), allocated on first use
+ * and kept by the context.  Synchronizes.  Errors: SGN_E_ARG
  * (t_end < t0, dt0 <= 0, negative or zero tolerances, max_attempts < 1),
  * SGN_E_UNSUPPORTED with a source term, SGN_E_NONFINITE when an error norm is
  * not finite, SGN_E_NONPOS_DEPTH when an accepted step leaves h <= 0 (q then
@@ -255,11 +259,12 @@ sgn_status sgn_rates(sgn_ctx* ctx, const void* q, double* mass_rate, double* ene
 sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
 
 /* Measurement: advance q by nsteps RK4 steps like sgn_step but with direct
- * launches, recording a HIP event on the context's stream between consecutive
- * kernels (all enqueued before the first wait, so the kernels run back to
- * back).  Four-stage path: ms[s] = mean duration of stage kernel s (0 = first,
- * 1 and 2 = middle, 3 = last).  Pair path: ms[0] = pair 1, ms[1] = pair 2,
- * ms[2] = ms[3] = 0.  Fused path: ms[0] = the step kernel, ms[1..3] = 0.  On
+ * launches, recording HIP events on the context's stream (all enqueued before
+ * the first wait, so the kernels run back to back).  Four-stage path: an event
+ * between consecutive kernels, ms[s] = mean duration of stage kernel s (0 =
+ * first, 1 and 2 = middle, 3 = last).  Pair path: likewise, ms[0] = pair 1,
+ * ms[1] = pair 2, ms[2] = ms[3] = 0.  Fused path (one kernel per step): events
+ * only around the measured launches, ms[0] = the step kernel, ms[1..3] = 0.  On
  * the pair and fused paths an odd nsteps is rounded up; the means leave out
  * the first step (two on those paths) when there are more.  nsteps <= 1024
  * (SGN_E_ARG otherwise).  Milliseconds; synchronizes. */

@@ -48,6 +48,43 @@ hipError_t launch_vjp(const sgn_ctx* c, hipStream_t s, const void* Y, const void
   return launch_vjp_t<float, ROLE>(c, s, Y, Kin, Qb, Kout, Acc, Bb, a_in, cq, cy);
 }
 
+template <typename T, int PAIR, int TX>
+hipError_t launch_vjp_pair_t(const sgn_ctx* c, hipStream_t s, const void* YA, const void* YB, const void* KinA,
+                             const void* Qb, void* QbOut, void* Kout, void* Acc, void* Bb, double aA, double cqA,
+                             double cyA, double cqB, double cyB) {
+  constexpr int TY = sgn::STEP_NODES / TX;
+  const int ntx = (c->p.nx + TX - 1) / TX;
+  const int nty = (c->p.ny + TY - 1) / TY;
+  const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
+#define SGN_VJPP(BX, BY)                                                                                         \
+  hipLaunchKernelGGL((sgn::vjp_pair_kernel<T, BX, BY, PAIR, TX>), grid, block, 0, s, c->gc, (const T*)YA,        \
+                     (const T*)YB, (const T*)c->b, (const T*)KinA, (const T*)Qb, (T*)QbOut, (T*)Kout, (T*)Acc,   \
+                     (T*)Bb, (T)aA, (T)cqA, (T)cyA, (T)cqB, (T)cyB)
+  const int bx = c->p.bc_x, by = c->p.bc_y;
+  if (bx == 0 && by == 0) SGN_VJPP(0, 0);
+  else if (bx == 0 && by == 1) SGN_VJPP(0, 1);
+  else if (bx == 1 && by == 0) SGN_VJPP(1, 0);
+  else SGN_VJPP(1, 1);
+#undef SGN_VJPP
+  return hipGetLastError();
+}
+
+// Two reverse stages in one launch (sgn::vjp_pair_kernel), on the step
+// kernel's tile shape.
+template <int PAIR>
+hipError_t launch_vjp_pair(const sgn_ctx* c, hipStream_t s, const void* YA, const void* YB, const void* KinA,
+                           const void* Qb, void* QbOut, void* Kout, void* Acc, void* Bb, double aA, double cqA,
+                           double cyA, double cqB, double cyB) {
+  if (c->p.dtype == SGN_F64) {
+    if (c->step_tile == 16)
+      return launch_vjp_pair_t<double, PAIR, 32>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
+    return launch_vjp_pair_t<double, PAIR, 64>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
+  }
+  if (c->step_tile == 16)
+    return launch_vjp_pair_t<float, PAIR, 32>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
+  return launch_vjp_pair_t<float, PAIR, 64>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
+}
+
 size_t state_bytes(const sgn_ctx* c) { return 5 * c->N * c->esize; }
 void* slot(void* base, size_t i, const sgn_ctx* c) { return (char*)base + i * state_bytes(c); }
 
@@ -136,14 +173,29 @@ hipError_t rollout_step(const sgn_ctx* c, hipStream_t s, void* cur, void* oth, d
 }
 
 // Reverse of one RK4 step whose stage states are Y1 = qn and ys = (Y2, Y3, Y4).
-// qbar: cotangent of q_{n+1} on entry, of q_n on exit; bbar accumulates.
+// qbar: cotangent of q_{n+1} on entry; the cotangent of q_n goes to *qbar_out:
+// qbar itself on the pair and four-stage paths (four role kernels, qbar
+// updated in place), the context's kb_b on the fused path (two launches of the
+// two-stage kernel, whose second one cannot write the qbar it reads on the
+// rings of its tiles).  bbar accumulates.
 hipError_t reverse_step(const sgn_ctx* c, hipStream_t s, const void* qn, const void* ys, void* qbar, void* bbar,
-                        double dt) {
+                        double dt, void** qbar_out) {
   const auto& a = c->adj;
   const void* y2 = slot((void*)ys, 0, c);
   const void* y3 = slot((void*)ys, 1, c);
   const void* y4 = slot((void*)ys, 2, c);
   hipError_t e;
+  if (c->step_path == SGN_PATH_FUSED) {
+    // S4 + S3: kb4 = dt/6 qb, kb3 = dt/3 qb + dt Yb4 (LDS); kb2 = dt/3 qb + dt/2 Yb3, acc = Yb4 + Yb3
+    if ((e = launch_vjp_pair<2>(c, s, y4, y3, qbar, qbar, nullptr, a.kb_a, a.accb, bbar, dt / 6.0, dt / 3.0, dt,
+                                dt / 3.0, dt / 2.0)))
+      return e;
+    // S2 + S1: kb1 = dt/6 qb + dt/2 Yb2 (LDS); qb_n = qb + (acc + Yb2) + Yb1
+    *qbar_out = a.kb_b;
+    return launch_vjp_pair<1>(c, s, y2, qn, a.kb_a, qbar, a.kb_b, nullptr, a.accb, bbar, 1.0, dt / 6.0, dt / 2.0,
+                              0.0, 0.0);
+  }
+  *qbar_out = qbar;
   // kb4 = dt/6 qb ; next kb3 = dt/3 qb + dt Yb4
   if ((e = launch_vjp<sgn::VJP_S4>(c, s, y4, qbar, qbar, a.kb_a, a.accb, bbar, dt / 6.0, dt / 3.0, dt))) return e;
   // kb2 = dt/3 qb + dt/2 Yb3
@@ -322,7 +374,9 @@ sgn_status sgn_step_vjp(sgn_ctx* c, const void* q_n, double dt, void* qbar, void
   void* ys = c->adj.stages;
   void* qnext = slot(c->adj.stages, 3, c);
   HIPCHK(c, forward_step_keep(c, c->stream, q_n, ys, qnext, dt));
-  HIPCHK(c, reverse_step(c, c->stream, q_n, ys, qbar, bbar, dt));
+  void* out = nullptr;
+  HIPCHK(c, reverse_step(c, c->stream, q_n, ys, qbar, bbar, dt, &out));
+  if (out != qbar) HIPCHK(c, hipMemcpyAsync(qbar, out, state_bytes(c), hipMemcpyDeviceToDevice, c->stream));
   return SGN_OK;
 }
 
@@ -415,8 +469,10 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, do
         hipLaunchKernelGGL(gauge_seed<float>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS), 0, s, gauge_idx, ngauges, c->N,
                            a.misfit + n * ngauges, (float*)a.qbar, (float*)grad_b);
       HIPCHK(c, hipGetLastError());
+      void* out = nullptr;
       HIPCHK(c, reverse_step(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),
-                             a.qbar, grad_b, dt));
+                             a.qbar, grad_b, dt, &out));
+      if (out != a.qbar) std::swap(a.qbar, a.kb_b);  // both buffers belong to the context
     }
   }
   // 3. reverse of the initialization

@@ -31,7 +31,7 @@ sgn_status ensure_buffers(sgn_ctx* c) {
   const size_t state = 5 * c->N * c->esize;
   const size_t part = 2 * (size_t)std::max(((c->p.nx + 63) / 64) * ((c->p.ny + 7) / 8), 1);
   bool ok = true;
-  for (void** p : {&f.k[0], &f.k[1], &f.ya, &f.yb, &f.e})
+  for (void** p : {&f.k[0], &f.k[1], &f.e})
     if (!*p) ok = ok && hipMalloc(p, state) == hipSuccess;
   if (ok && f.part_cap < part) {
     if (f.part) (void)hipFree(f.part);
@@ -64,8 +64,8 @@ hipError_t enqueue_attempt_ty(const sgn_ctx* c, hipStream_t s, void* q, double* 
   a.q[1] = (T*)c->acc;
   a.k[0] = (T*)f.k[0];
   a.k[1] = (T*)f.k[1];
-  a.ya = (T*)f.ya;
-  a.yb = (T*)f.yb;
+  a.ya = (T*)c->ya;  // the stage states of the role kernels: the context's own
+  a.yb = (T*)c->yb;
   a.e = (T*)f.e;
   a.b = (const T*)c->b;
   a.part = f.part;
@@ -78,10 +78,22 @@ hipError_t enqueue_attempt_ty(const sgn_ctx* c, hipStream_t s, void* q, double* 
     else if (bx == 1 && by == 0) hipLaunchKernelGGL((sgn::fsal_kernel<T, 1, 0, R, TY>), grid, block, 0, s, c->gc, a); \
     else hipLaunchKernelGGL((sgn::fsal_kernel<T, 1, 1, R, TY>), grid, block, 0, s, c->gc, a);                \
   } while (0)
-  SGN_ROLE(sgn::FS_S2);
-  SGN_ROLE(sgn::FS_S3);
-  SGN_ROLE(sgn::FS_S4);
-  SGN_ROLE(sgn::FS_S5);
+  if (c->step_path == SGN_PATH_FUSED) {
+    // S2 .. S5 in one launch of the step tile
+    constexpr int TXA = 64, TXB = 32;
+    const int tx = c->step_tile == 16 ? TXB : TXA;
+    const int sx = (c->p.nx + tx - 1) / tx, sy = (c->p.ny + sgn::STEP_NODES / tx - 1) / (sgn::STEP_NODES / tx);
+    const dim3 sgrid((unsigned)(sx * sy));
+#define SGN_FSTEP(TX)                                                                                            do {                                                                                                             if (bx == 0 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 0, TX>), sgrid, block, 0, s, c->gc, a);     else if (bx == 0 && by == 1) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 1, TX>), sgrid, block, 0, s, c->gc, a);     else if (bx == 1 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 0, TX>), sgrid, block, 0, s, c->gc, a);     else hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 1, TX>), sgrid, block, 0, s, c->gc, a);                  } while (0)
+    if (tx == TXB) SGN_FSTEP(TXB);
+    else SGN_FSTEP(TXA);
+#undef SGN_FSTEP
+  } else {
+    SGN_ROLE(sgn::FS_S2);
+    SGN_ROLE(sgn::FS_S3);
+    SGN_ROLE(sgn::FS_S4);
+    SGN_ROLE(sgn::FS_S5);
+  }
   SGN_ROLE(sgn::FS_FSAL);
 #undef SGN_ROLE
   hipLaunchKernelGGL(sgn::fsal_control, dim3(1), dim3(sgn::RED_THREADS), 0, s, (sgn::AdaptCtl*)f.ctl, f.part, nt,
@@ -100,7 +112,8 @@ hipError_t enqueue_attempt(const sgn_ctx* c, hipStream_t s, void* q, double* rec
 sgn_status get_graph(sgn_ctx* c, void* q, double* rec, long long rec_cap, hipGraphExec_t* out) {
   auto& f = c->fs;
   auto& g = f.graph;
-  if (g.exec && g.q == q && g.tile_y == c->tile_y && f.graph_rec == rec && f.graph_rec_cap == rec_cap) {
+  if (g.exec && g.q == q && g.tile_y == c->tile_y && g.path == c->step_path && g.step_tile == c->step_tile &&
+      f.graph_rec == rec && f.graph_rec_cap == rec_cap) {
     *out = g.exec;
     return SGN_OK;
   }
@@ -123,6 +136,8 @@ sgn_status get_graph(sgn_ctx* c, void* q, double* rec, long long rec_cap, hipGra
   g.exec = exec;
   g.q = q;
   g.tile_y = c->tile_y;
+  g.path = c->step_path;
+  g.step_tile = c->step_tile;
   f.graph_rec = rec;
   f.graph_rec_cap = rec_cap;
   *out = exec;
@@ -136,7 +151,7 @@ namespace sgn_host {
 void free_fsal(sgn_ctx* c) {
   auto& f = c->fs;
   if (f.graph.exec) (void)hipGraphExecDestroy(f.graph.exec);
-  for (void* p : {f.k[0], f.k[1], f.ya, f.yb, f.e, f.ctl})
+  for (void* p : {f.k[0], f.k[1], f.e, f.ctl})
     if (p) (void)hipFree(p);
   if (f.part) (void)hipFree(f.part);
   if (f.host_ctl) (void)hipHostFree(f.host_ctl);

@@ -22,8 +22,9 @@
 // after a rejection; errp = the last accepted err, at least 1e-4); a rejected
 // step is retried with h max(0.2, 0.9 err^(-1/3)); the last step ends at t_end.
 //
-// One attempt is five launches over 64 x TY tiles with a one-node halo (the
-// layout and right-hand side of the stage kernel) and a one-block controller:
+// On the four-stage and pair step paths one attempt is five launches over
+// 64 x TY tiles with a one-node halo (the layout and right-hand side of the
+// stage kernel) and a one-block controller:
 //   S2:   stages Y_2 = y + h c_2 k_1 (formed while staging from y and k_1),
 //         writes acc = y + h b_1 k_1 + h b_2 k_2 into the other state buffer
 //         and Y_3 = y + h c_3 k_2                               21 values/node
@@ -35,6 +36,8 @@
 //         compensated sums of the scaled squares, health check   21
 //   control: merges the tile sums in tile order, accepts or rejects, updates
 //         t, h, the counters and the buffer selector in device memory.
+// On the default (fused) step path S2 .. S5 are one launch of the step tile
+// (fsal_step_kernel): 21 + 21 values per node and attempt instead of 120.
 // The state buffer holding y_n and the one holding k_1 are selected by a
 // device-side index that flips on acceptance, so a rejected attempt leaves
 // y_n and k_1 untouched and no copy is needed.  Every kernel returns at once
@@ -42,6 +45,7 @@
 // the end.
 #pragma once
 
+#include "sgn_fused.hpp"
 #include "sgn_reduce.hpp"
 #include "sgn_stage.hpp"
 
@@ -247,6 +251,42 @@ __global__ __launch_bounds__(STAGE_THREADS) void fsal_kernel(const GridConst gc,
       a.part[2 * tile + 1] = arr[0].c;
     }
   }
+}
+
+// S2 .. S5 of one attempt in one launch (the default step path): the step
+// tile in its RK_FSAL mode over TX x (512 / TX) tiles with a four-node halo.
+// Reads y, k_1 and b, writes y_{n+1} and e'; the intermediate stages Y_2 .. Y_5
+// stay in LDS (the rings around each tile are evaluated redundantly).  21
+// values per node instead of the 99 of the four role kernels.  Same arithmetic
+// as the roles node by node, so the same bits.
+template <typename T, int BCX, int BCY, int TX>
+__global__ __launch_bounds__(STAGE_THREADS) void fsal_step_kernel(const GridConst gc, const FsalArgs<T> a) {
+  constexpr int TY = StepGeom<TX>::TY;
+  __shared__ StepSmem<T, TX, 1> s;
+  const AdaptCtl* ctl = a.ctl;
+  if (ctl->done) return;  // the same for the whole grid
+  const int cur = ctl->cur;
+  const double h = ctl->h;
+  using C = Fsal35;
+  FsalStage<T> fx;
+  fx.k1 = a.k[cur];
+  fx.e = a.e;
+  fx.cin = T(h * C::c2);
+  fx.c1a = T(h * C::b1);
+  fx.cy[0] = T(h * C::c3);
+  fx.cy[1] = T(h * C::c4);
+  fx.cy[2] = T(h * C::c5);
+  fx.ca[0] = T(h * C::b2);
+  fx.ca[1] = T(h * C::b3);
+  fx.ca[2] = T(h * C::b4);
+  fx.ca[3] = T(h * C::b5);
+  fx.ce1 = T(h * C::b5 * (1.0 - C::c5));
+  const int ntx = (gc.nx + TX - 1) / TX;
+  const int nty = (gc.ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  step_tile<T, BCX, BCY, false, TX, false, 1, EPI_NONE, RK_FSAL>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY,
+                                                                 a.q[cur], a.b, a.q[cur ^ 1], T(0), T(0), T(0),
+                                                                 T(0), 0.0, 0.0, nullptr, nullptr, nullptr, &fx);
 }
 
 // One block: merges the tile sums in tile order into err and applies the

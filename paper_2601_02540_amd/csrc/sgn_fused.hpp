@@ -71,6 +71,29 @@ __device__ __forceinline__ Node<T> opaque_node(Node<T> n) {
   return n;
 }
 
+// Which Runge-Kutta method a step tile runs.  RK_CLASSIC: one classical RK4
+// step from q.  RK_FSAL: evaluations 2 to 5 of one attempt of the adaptive
+// five-stage pair (sgn_fsal.hpp): the tile stages Y_2 = y + h c_2 k_1 (from
+// the input y and the attempt's k_1), evaluates k_2 .. k_5 on the shrinking
+// regions, and writes y_{n+1} = y + h (b_1 k_1 + ... + b_5 k_5) and the partial
+// error estimate e' = h b_5 (k_5 - (1 - c_5) k_1) of the owned nodes.  The
+// tile first stages y, from which the owned and ring nodes keep their y in
+// registers (as the classical step keeps q), then overwrites it with Y_2; k_1
+// of the owned nodes is read again from global memory (L2).
+enum : int { RK_CLASSIC = 0, RK_FSAL = 1 };
+
+// Coefficients and extra operands of an RK_FSAL tile (h already applied).
+template <typename T>
+struct FsalStage {
+  const T* k1;  // k_1 of the attempt
+  T* e;         // out: e' of the owned nodes
+  T cin;        // h c_2
+  T c1a;        // h b_1
+  T cy[3];      // evaluation s = k_{s+1}: Y_{s+2} = y + cy[s-1] k_{s+1}  (s = 1, 2, 3)
+  T ca[4];      // acc += ca[s-1] k_{s+1}                                  (s = 1 .. 4)
+  T ce1;        // h b_5 (1 - c_5)
+};
+
 // Position (r, c), relative to the tile origin, of ring node m (0 <= m < RING3).
 template <int TX>
 __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
@@ -109,12 +132,19 @@ __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
 // enum; from the step's input and output values held in registers) into
 // rpart[0..3].
 // The caller synchronizes the workgroup before reusing `s` for another tile.
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, int EPI = EPI_NONE>
+// RK = RK_FSAL (no source, no stage saving, no epilogue): q is the attempt's
+// y_n, qout receives y_{n+1}, *fx supplies k_1, the coefficients and the e'
+// output; c6 .. c1, t0, dt and flag are unused (the health of y_{n+1} is
+// checked by the attempt's FSAL evaluation).
+template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, int EPI = EPI_NONE,
+          int RK = RK_CLASSIC>
 __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridConst& gc, int i0, int j0,
                                           const T* __restrict__ q, const T* __restrict__ bplane,
                                           T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
                                           int* __restrict__ flag, T* __restrict__ ysave,
-                                          double* __restrict__ rpart = nullptr) {
+                                          double* __restrict__ rpart = nullptr,
+                                          const FsalStage<T>* __restrict__ fx = nullptr) {
+  static_assert(RK == RK_CLASSIC || (!SRC && !SAVE && EPI == EPI_NONE), "the FSAL tile has no extras");
   using G = StepGeom<TX>;
   constexpr int RX = G::RX;
   constexpr int REGION = G::RX * G::RY;
@@ -127,9 +157,12 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   //    Every load of the region is issued before the first one is waited
   //    for: the step kernel reads little per unit of work, so its bandwidth
   //    is set by how many bytes each workgroup keeps in flight.
+  constexpr int NF = RK == RK_FSAL ? 2 : 1;
+  T yown[NF][5], yring[NF][5];  // RK_FSAL: y of the owned and ring nodes
   {
     constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
     T v[ITER][6];
+    T kst[RK == RK_FSAL ? ITER : 1][5];
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int idx = tid + it * STAGE_THREADS;
@@ -142,6 +175,10 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
 #pragma unroll
         for (int f = 0; f < 5; ++f) v[it][f] = q[f * N + o];
         v[it][5] = bplane[o];
+        if constexpr (RK == RK_FSAL) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) kst[it][f] = fx->k1[f * N + o];
+        }
       }
     }
 #pragma unroll
@@ -152,7 +189,42 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
         const int cc = idx - rr * RX;
 #pragma unroll
         for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
-        s.f[6][rr][cc] = recip_staged(v[it][0]);
+        if constexpr (RK == RK_CLASSIC) s.f[6][rr][cc] = recip_staged(v[it][0]);
+      }
+    }
+    if constexpr (RK == RK_FSAL) {
+      __syncthreads();
+      // LDS holds y: the owned and ring nodes take their y from it (the ring's
+      // periodic images and clamped wall copies included), then Y_2 =
+      // y + h c_2 k_1 and its 1/h replace it
+      const int lx_ = tid % TX, ly_ = 2 * (tid / TX);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) yown[k][f] = s.f[f][ly_ + k + STEP_HALO][lx_ + STEP_HALO];
+        const int m = tid + k * STAGE_THREADS;
+        if (m < G::RING3) {
+          int r_, c_;
+          ring_node<TX>(m, r_, c_);
+#pragma unroll
+          for (int f = 0; f < 5; ++f) yring[k][f] = s.f[f][r_ + STEP_HALO][c_ + STEP_HALO];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < ITER; ++it) {
+        const int idx = tid + it * STAGE_THREADS;
+        if (idx < REGION) {
+          const int rr = idx / RX;
+          const int cc = idx - rr * RX;
+          T y2[5];
+#pragma unroll
+          for (int f = 0; f < 5; ++f) {
+            y2[f] = v[it][f] + fx->cin * kst[it][f];
+            s.f[f][rr][cc] = y2[f];
+          }
+          s.f[6][rr][cc] = recip_staged(y2[0]);
+        }
       }
     }
   }
@@ -183,6 +255,23 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   __syncthreads();
 
   T qo[2][5], acc[2][5], qr[2][5];
+  T k1o[NF][5];  // RK_FSAL: k_1 of the owned nodes
+  if constexpr (RK == RK_FSAL) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qo[k][f] = yown[k][f];
+      if (tid + k * STAGE_THREADS < G::RING3) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) qr[k][f] = yring[k][f];
+      }
+      if (own_dom[k]) {
+        const size_t ow = (size_t)wrap_or_clamp<BCY>(j0 + ly0 + k, ny) * nx + wrap_or_clamp<BCX>(i, nx);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) k1o[k][f] = fx->k1[f * N + ow];
+      }
+    }
+  }
   int health = 0;
   CSum rsum[2];
   if (EPI != EPI_NONE) {
@@ -191,8 +280,12 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   }
 #pragma unroll
   for (int st = 1; st <= 4; ++st) {
-    const T cy = st == 3 ? c1 : c2;     // Y_{st+1} = q + cy k_st
-    const T ca = st == 1 || st == 4 ? c6 : c3;  // acc += ca k_st
+    T cy = st == 3 ? c1 : c2;             // Y_{st+1} = q + cy k_st
+    T ca = st == 1 || st == 4 ? c6 : c3;  // acc += ca k_st
+    if constexpr (RK == RK_FSAL) {
+      cy = st < 4 ? fx->cy[st - 1] : T(0);
+      ca = fx->ca[st - 1];
+    }
     const double ts = t0 + (st == 1 ? 0.0 : (st == 4 ? dt : 0.5 * dt));
     const int ring_lim = st == 1 ? G::RING3 : (st == 2 ? G::RING2 : G::RING1);
     T ro[2][5], rr[2][5];
@@ -203,7 +296,21 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     const auto finish = [&](int k, const Rates<T>& kk, const Node<T>& cn) {
       const int j = j0 + ly0 + k;
       const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
-      if (st == 1) {
+      if constexpr (RK == RK_FSAL) {
+        if (st == 1) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) {
+            acc[k][f] = qo[k][f] + fx->c1a * k1o[k][f] + ca * kv[f];
+            ro[k][f] = qo[k][f] + cy * kv[f];
+          }
+        } else if (st < 4) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) {
+            acc[k][f] = acc[k][f] + ca * kv[f];
+            ro[k][f] = qo[k][f] + cy * kv[f];
+          }
+        }
+      } else if (st == 1) {
         const T yv[5] = {cn.h, cn.u, cn.v, cn.w, cn.eta};
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
@@ -231,9 +338,14 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
           nv[f] = acc[k][f] + ca * kv[f];
           qout[f * N + o] = nv[f];
         }
-        if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
-        const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
-        if (!isfinite(sum)) health |= FLAG_NONFINITE;
+        if constexpr (RK == RK_FSAL) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) fx->e[f * N + o] = ca * kv[f] - fx->ce1 * k1o[k][f];
+        } else {
+          if (!(nv[0] > T(0))) health |= FLAG_NONPOS;
+          const T sum = nv[0] + nv[1] + nv[2] + nv[3] + nv[4];
+          if (!isfinite(sum)) health |= FLAG_NONFINITE;
+        }
         if (EPI == EPI_TOTALS) {
           const double M = axis_weight(i, nx, gc.bc_x, gc.dx) * axis_weight(j, ny, gc.bc_y, gc.dy);
           const double bb = (double)s.f[5][ly0 + k + STEP_HALO][lx + STEP_HALO];
@@ -299,12 +411,14 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
       const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ring_r[k] + STEP_HALO, ring_c[k] + STEP_HALO,
                                                       i0 + ring_c[k], j0 + ring_r[k], gc, ts, cn);
       const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
-      if (st == 1) {
-        qr[k][0] = cn.h;
-        qr[k][1] = cn.u;
-        qr[k][2] = cn.v;
-        qr[k][3] = cn.w;
-        qr[k][4] = cn.eta;
+      if constexpr (RK == RK_CLASSIC) {
+        if (st == 1) {
+          qr[k][0] = cn.h;
+          qr[k][1] = cn.u;
+          qr[k][2] = cn.v;
+          qr[k][3] = cn.w;
+          qr[k][4] = cn.eta;
+        }
       }
 #pragma unroll
       for (int f = 0; f < 5; ++f) rr[k][f] = qr[k][f] + cy * kv[f];
@@ -330,7 +444,9 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     }
     __syncthreads();
   }
-  if (health) atomicOr(flag, health);
+  if constexpr (RK == RK_CLASSIC) {
+    if (health) atomicOr(flag, health);
+  }
   if (EPI != EPI_NONE) {
     block_merge<2>(rsum);
     if (tid == 0) {

@@ -39,8 +39,6 @@ struct AdjointBuffers {
 // Buffers of the adaptive pair (sgn_step_adaptive), allocated on first use.
 struct FsalBuffers {
   void* k[2] = {nullptr, nullptr};  // k_1 of the current step / of the next one (FSAL)
-  void* ya = nullptr;               // stage states (ping-pong)
-  void* yb = nullptr;
   void* e = nullptr;                // partial error estimate
   double* part = nullptr;           // per-tile sums of the scaled squares
   size_t part_cap = 0;              // doubles in part

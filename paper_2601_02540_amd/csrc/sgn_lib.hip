@@ -695,12 +695,13 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   const bool pairs = c->step_path == SGN_PATH_PAIRS;
   const bool fused = c->step_path == SGN_PATH_FUSED;
   if ((pairs || fused) && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
-  const int nk = fused ? 2 : 4;                      // launches recorded per profiled unit
+  const int nk = fused ? 0 : 4;                      // events between the launches of a profiled unit
   const int64_t units = (pairs || fused) ? nsteps / 2 : nsteps;
-  // One event between consecutive launches, all enqueued before the first
-  // wait, so the kernels run back to back as in a timed run; with more than
-  // one unit the first (warm-up) unit is left out of the means.
-  std::vector<hipEvent_t> ev((size_t)(units * nk + 1), nullptr);
+  // One event between consecutive launches (fused path: one kernel per step,
+  // so only around the launches), all enqueued before the first wait, so the
+  // kernels run back to back as in a timed run; with more than one unit the
+  // first (warm-up) unit is left out of the means.
+  std::vector<hipEvent_t> ev(fused ? 3 : (size_t)(units * nk + 1), nullptr);
   hipError_t e = hipSuccess;
   for (auto& x : ev)
     if (!e) e = hipEventCreate(&x);
@@ -709,11 +710,10 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   for (int64_t u = 0; u < units && e == hipSuccess; ++u) {
     const double t = (double)u * ((pairs || fused) ? 2.0 : 1.0) * dt;
     if (fused) {
-      // two consecutive steps (q -> acc -> q)
+      // two consecutive steps (q -> acc -> q); an event after the first unit and after the last
       e = launch_fused(c, c->stream, q, c->acc, dt, t);
-      if (!e) e = hipEventRecord(ev[n++], c->stream);
       if (!e) e = launch_fused(c, c->stream, c->acc, q, dt, t + dt);
-      if (!e) e = hipEventRecord(ev[n++], c->stream);
+      if (!e && (u == 0 || u == units - 1) && n < 3) e = hipEventRecord(ev[n++], c->stream);
     } else if (pairs) {
       // pair 1 and pair 2 of two consecutive steps (q -> acc -> q)
       e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
@@ -738,7 +738,12 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if (!e) e = hipEventSynchronize(ev[n - 1]);
   double acc_ms[4] = {0, 0, 0, 0};
   const int64_t first = units > 1 ? 1 : 0;
-  for (int64_t u = first; u < units && !e; ++u)
+  if (fused && !e) {
+    float m = 0.f;
+    e = hipEventElapsedTime(&m, ev[first], ev[first + 1]);  // units first .. units-1
+    acc_ms[0] = m;
+  }
+  for (int64_t u = first; u < units && !e && !fused; ++u)
     for (int k = 0; k < nk && !e; ++k) {
       float m = 0.f;
       e = hipEventElapsedTime(&m, ev[(size_t)(u * nk + k)], ev[(size_t)(u * nk + k + 1)]);
@@ -750,7 +755,7 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   const double used = (double)(units - first);
   if (fused) {
     // ms[0] = one fused step (mean over both steps of each unit)
-    ms[0] = (acc_ms[0] + acc_ms[1]) / (2.0 * used);
+    ms[0] = acc_ms[0] / (2.0 * used);
     ms[1] = ms[2] = ms[3] = 0.0;
   } else if (pairs) {
     // ms[0] = pair 1, ms[1] = pair 2 (means over both steps of each unit)

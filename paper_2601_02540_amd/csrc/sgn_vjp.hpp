@@ -19,8 +19,12 @@
 //   (D^T Dbar)(d) = D[d-1][d] Dbar(d-1) + D[d][d] Dbar(d) + D[d+1][d] Dbar(d+1)
 // (AxisTranspose below, closure rows included), then chains the amounts back
 // through the products at d.  No value crosses threads except through LDS.
+// The diagonal D[d][d] vanishes except on the first and last row of a
+// reflecting axis, so only those nodes evaluate their own Dbar; the reverse of
+// a node's own rates (split_form_reverse) therefore stops at its raw values.
 #pragma once
 
+#include "sgn_fused.hpp"
 #include "sgn_stage.hpp"
 
 namespace sgn {
@@ -78,14 +82,15 @@ __device__ __forceinline__ Cot<T> chain_y(const Node<T>& n, const T (&a)[12]) {
   return c;
 }
 
-// Reverse of split_form_rates at one node.  Outputs the cotangent of the node's
-// own raw values (center) and the derivative cotangents dX[12], dY[12] (of the
-// derivative values themselves, before the stencil scale).
+// Reverse of split_form_rates at one node, through the node's own values: the
+// cotangent of the node's raw values (center) from the seed kb of its rates.
+// The cotangents of the node's derivative values, dbar_x and dbar_y of the node
+// itself (below), reach the node's own values only through the diagonal of
+// the operator, i.e. on the reflecting closure rows.
 template <typename T>
 __device__ __forceinline__ void split_form_reverse(const Node<T>& c, const Node<T>& xm, const Node<T>& xp,
                                                    const Node<T>& ym, const Node<T>& yp, T sx, T sy, T g, T lam,
-                                                   T satx, T saty, const T (&kb)[5], Cot<T>& cen, T (&dX)[12],
-                                                   T (&dY)[12]) {
+                                                   T satx, T saty, const T (&kb)[5], Cot<T>& cen) {
   const T half = T(0.5);
   // forward values
   const T Dxh = sx * (xp.h - xm.h), Dxu = sx * (xp.u - xm.u), Dxv = sx * (xp.v - xm.v), Dxw = sx * (xp.w - xm.w);
@@ -121,10 +126,6 @@ __device__ __forceinline__ void split_form_reverse(const Node<T>& c, const Node<
   const T C = half * (Dxhuw + hu * Dxw - u * w * Dxh - hw * Dxu + Dyhvw + hv * Dyw - v * w * Dyh - hw * Dyv);
 
   const T ah = kb[0], au = kb[1], av = kb[2], aw = kb[3], ae = kb[4];
-  for (int k = 0; k < 12; ++k) {
-    dX[k] = T(0);
-    dY[k] = T(0);
-  }
   const T Ab = -au * ih, Bb = -av * ih, Cb = -aw * ih;
   T ihb = -au * A - av * B + aw * (lam * omr - C);
   T omrb = lam * aw * ih;
@@ -133,85 +134,41 @@ __device__ __forceinline__ void split_form_reverse(const Node<T>& c, const Node<
   wb = ae;
   ub = -ae * (Dxeta + T(1.5) * Dxb);
   vb = -ae * (Dyeta + T(1.5) * Dyb);
-  dX[4] = -ae * u;
-  dY[4] = -ae * v;
-  dX[5] = -T(1.5) * ae * u;
-  dY[5] = -T(1.5) * ae * v;
   // k_h = -(u Dxh + h Dxu + v Dyh + h Dyv) + satx hu + saty hv
   ub += -ah * Dxh;
-  dX[0] = -ah * u;
   hb = -ah * (Dxu + Dyv);
-  dX[1] = -ah * h;
   vb += -ah * Dyh;
-  dY[0] = -ah * v;
-  dY[2] = -ah * h;
   hub = ah * satx;
   hvb = ah * saty;
   // A
-  dX[6] += g * Ab;
   Hb = -g * Ab * Dxh;
-  dX[0] += -g * Ab * H;
   hb += half * Ab * Dxu2;
-  dX[7] += half * Ab * h;
   ub += -Ab * u * Dxh;
-  dX[0] += -half * Ab * u * u;
   ub += half * Ab * Dxhu;
-  dX[8] += half * Ab * u;
   hub += -half * Ab * Dxu;
-  dX[1] += -half * Ab * hu;
-  dY[9] += half * Ab;
   uvb = -half * Ab * Dyh;
-  dY[0] += -half * Ab * uv;
   hvb += half * Ab * Dyu;
-  dY[1] += half * Ab * hv;
   hub += -half * Ab * Dyv;
-  dY[2] += -half * Ab * hu;
   rb = lam3 * Ab * r * Dxh;
-  dX[0] += lam6 * Ab * r * r;
-  dX[10] += -lam6 * Ab;
   omrb += lam3 * Ab * Dxeta + lam2 * Ab * Dxb;
-  dX[4] += lam3 * Ab * omr;
-  dX[5] += lam2 * Ab * omr;
   // B
-  dY[6] += g * Bb;
   Hb += -g * Bb * Dyh;
-  dY[0] += -g * Bb * H;
   hb += half * Bb * Dyv2;
-  dY[7] += half * Bb * h;
   vb += -Bb * v * Dyh;
-  dY[0] += -half * Bb * v * v;
   vb += half * Bb * Dyhv;
-  dY[8] += half * Bb * v;
   hvb += -half * Bb * Dyv;
-  dY[2] += -half * Bb * hv;
-  dX[9] += half * Bb;
   uvb += -half * Bb * Dxh;
-  dX[0] += -half * Bb * uv;
   hub += half * Bb * Dxv;
-  dX[2] += half * Bb * hu;
   hvb += -half * Bb * Dxu;
-  dX[1] += -half * Bb * hv;
   rb += lam3 * Bb * r * Dyh;
-  dY[0] += lam6 * Bb * r * r;
-  dY[10] += -lam6 * Bb;
   omrb += lam3 * Bb * Dyeta + lam2 * Bb * Dyb;
-  dY[4] += lam3 * Bb * omr;
-  dY[5] += lam2 * Bb * omr;
   // C
-  dX[11] += half * Cb;
   hub += half * Cb * Dxw;
-  dX[3] += half * Cb * hu;
   uwb = -half * Cb * Dxh;
-  dX[0] += -half * Cb * uw;
   hwb = -half * Cb * Dxu;
-  dX[1] += -half * Cb * hw;
-  dY[11] += half * Cb;
   hvb += half * Cb * Dyw;
-  dY[3] += half * Cb * hv;
   vwb = -half * Cb * Dyh;
-  dY[0] += -half * Cb * vw;
   hwb += -half * Cb * Dyv;
-  dY[2] += -half * Cb * hw;
   // center products
   rb += -omrb;
   hb += Hb;
@@ -319,13 +276,19 @@ __device__ __forceinline__ void dbar_y(const Node<T>& n, const Seed<T>& a, T g, 
   q[11] = half * Cb;
 }
 
+template <typename T>
+__device__ __forceinline__ Seed<T> opaque_seed(Seed<T> a) {
+  asm volatile("" : "+v"(a.h), "+v"(a.u), "+v"(a.v), "+v"(a.w), "+v"(a.eta));
+  return a;
+}
+
 template <typename T, int TY>
 struct VjpSmem {
   T f[12][TY + 2][TILE_X + 2];  // h u v w eta b 1/h | seeds of h u v w eta
 };
 
-template <typename T, int TY>
-__device__ __forceinline__ void vjp_lds(const VjpSmem<T, TY>& s, int r, int c, Node<T>& n, Seed<T>& a) {
+template <typename T, class Smem>
+__device__ __forceinline__ void vjp_lds(const Smem& s, int r, int c, Node<T>& n, Seed<T>& a) {
   n.h = s.f[0][r][c];
   n.u = s.f[1][r][c];
   n.v = s.f[2][r][c];
@@ -338,6 +301,82 @@ __device__ __forceinline__ void vjp_lds(const VjpSmem<T, TY>& s, int r, int c, N
   a.v = s.f[9][r][c];
   a.w = s.f[10][r][c];
   a.eta = s.f[11][r][c];
+}
+
+// Cotangent of the raw values of node (i, j), in the domain: the reverse of
+// its own rates plus what its neighbours' derivatives send it (the gathered
+// transpose), from a staging s that holds Y, b, 1/h and the seeds (planes
+// 0..11) around the node's position (r, c).
+template <typename T, int BCX, int BCY, class Smem>
+__device__ __forceinline__ Cot<T> vjp_node(const Smem& s, int r, int c, int i, int j, const GridConst& gc) {
+  const int nx = gc.nx, ny = gc.ny;
+  const T g = T(gc.g), lam = T(gc.lam);
+  const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
+  const AxisTranspose<T, BCX> tx_(i, nx, gc.inv2dx, gc.invdx);
+  T satx = T(0);
+  if (BCX == BC_REFLECTING) {
+    if (i == 0) satx = T(-2.0 * gc.invdx);
+    if (i == nx - 1) satx = T(2.0 * gc.invdx);
+  }
+  const AxisStencil<BCY> ay(j, ny, gc.inv2dy, gc.invdy);
+  const AxisTranspose<T, BCY> ty_(j, ny, gc.inv2dy, gc.invdy);
+  T saty = T(0);
+  if (BCY == BC_REFLECTING) {
+    if (j == 0) saty = T(-2.0 * gc.invdy);
+    if (j == ny - 1) saty = T(2.0 * gc.invdy);
+  }
+  Node<T> nc, nxm, nxp, nym, nyp;
+  Seed<T> ac, axm, axp, aym, ayp;
+  vjp_lds(s, r, c, nc, ac);
+  vjp_lds(s, r, c - 1, nxm, axm);
+  vjp_lds(s, r, c + 1, nxp, axp);
+  vjp_lds(s, r - 1, c, nym, aym);
+  vjp_lds(s, r + 1, c, nyp, ayp);
+  // Opaque copies: where one thread evaluates neighbouring nodes, the compiler
+  // would otherwise share loads and products between the evaluations and fuse
+  // the arithmetic differently; every evaluation rounds as a lone one does.
+  nc = opaque_node(nc);
+  nxm = opaque_node(nxm);
+  nxp = opaque_node(nxp);
+  nym = opaque_node(nym);
+  nyp = opaque_node(nyp);
+  ac = opaque_seed(ac);
+  axm = opaque_seed(axm);
+  axp = opaque_seed(axp);
+  aym = opaque_seed(aym);
+  ayp = opaque_seed(ayp);
+  // local part: reverse of this node's own rates (stencil neighbours with closures)
+  const Node<T>& sxm = ax.om == 0 ? nc : nxm;
+  const Node<T>& sxp = ax.op == 0 ? nc : nxp;
+  const Node<T>& sym = ay.om == 0 ? nc : nym;
+  const Node<T>& syp = ay.op == 0 ? nc : nyp;
+  const T kb[5] = {ac.h, ac.u, ac.v, ac.w, ac.eta};
+  Cot<T> out;
+  split_form_reverse<T>(nc, sxm, sxp, sym, syp, T(ax.scale), T(ay.scale), g, lam, satx, saty, kb, out);
+  // transpose part: Dbar of the neighbours, and of this node itself where
+  // the operator's diagonal is nonzero (the closure rows of a reflecting axis)
+  T qa[12], qb[12], amt[12];
+  dbar_x(nxm, axm, g, lam, qa);
+  dbar_x(nxp, axp, g, lam, qb);
+#pragma unroll
+  for (int m = 0; m < 12; ++m) amt[m] = tx_.wl * qa[m] + tx_.wr * qb[m];
+  if (BCX == BC_REFLECTING && (i == 0 || i == nx - 1)) {
+    dbar_x(nc, ac, g, lam, qa);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) amt[m] += tx_.wc * qa[m];
+  }
+  out.add(chain_x(nc, amt));
+  dbar_y(nym, aym, g, lam, qa);
+  dbar_y(nyp, ayp, g, lam, qb);
+#pragma unroll
+  for (int m = 0; m < 12; ++m) amt[m] = ty_.wl * qa[m] + ty_.wr * qb[m];
+  if (BCY == BC_REFLECTING && (j == 0 || j == ny - 1)) {
+    dbar_y(nc, ac, g, lam, qa);
+#pragma unroll
+    for (int m = 0; m < 12; ++m) amt[m] += ty_.wc * qa[m];
+  }
+  out.add(chain_y(nc, amt));
+  return out;
 }
 
 // One reverse-mode stage (role ROLE) on a 64 x TY tile per workgroup.
@@ -362,90 +401,73 @@ __global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, 
   const int tx = tid & (TILE_X - 1);
   const int ty = tid >> 6;
 
-  for (int idx = tid; idx < REGION; idx += STAGE_THREADS) {
-    const int rr = idx / W;
-    const int cc = idx - rr * W;
-    int gi = i0 - 1 + cc;
-    int gj = j0 - 1 + rr;
-    if (BCX == BC_PERIODIC) {
-      if (gi < 0) gi += nx;
-      while (gi >= nx) gi -= nx;
-    } else {
-      gi = gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi);
-    }
-    if (BCY == BC_PERIODIC) {
-      if (gj < 0) gj += ny;
-      while (gj >= ny) gj -= ny;
-    } else {
-      gj = gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj);
-    }
-    const size_t o = (size_t)gj * nx + gi;
-    const T h = Y[o];
-    s.f[0][rr][cc] = h;
-    s.f[1][rr][cc] = Y[N + o];
-    s.f[2][rr][cc] = Y[2 * N + o];
-    s.f[3][rr][cc] = Y[3 * N + o];
-    s.f[4][rr][cc] = Y[4 * N + o];
-    s.f[5][rr][cc] = bplane[o];
-    s.f[6][rr][cc] = recip_staged(h);
+  // Stage Y, b and the scaled seeds with a one-node halo.  Every load of the
+  // region is issued before the first LDS write waits for one, so each
+  // workgroup keeps the whole region in flight.
+  {
+    constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
+    T v[ITER][11];
 #pragma unroll
-    for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = a_in * Kin[f * N + o];
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGION) {
+        const int rr = idx / W;
+        const int cc = idx - rr * W;
+        int gi = i0 - 1 + cc;
+        int gj = j0 - 1 + rr;
+        if (BCX == BC_PERIODIC) {
+          if (gi < 0) gi += nx;
+          while (gi >= nx) gi -= nx;
+        } else {
+          gi = gi < 0 ? 0 : (gi >= nx ? nx - 1 : gi);
+        }
+        if (BCY == BC_PERIODIC) {
+          if (gj < 0) gj += ny;
+          while (gj >= ny) gj -= ny;
+        } else {
+          gj = gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj);
+        }
+        const size_t o = (size_t)gj * nx + gi;
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[it][f] = Y[f * N + o];
+        v[it][5] = bplane[o];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[it][6 + f] = Kin[f * N + o];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGION) {
+        const int rr = idx / W;
+        const int cc = idx - rr * W;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
+        s.f[6][rr][cc] = recip_staged(v[it][0]);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = a_in * v[it][6 + f];
+      }
+    }
   }
   __syncthreads();
 
-  const T g = T(gc.g), lam = T(gc.lam);
   const int i = i0 + tx;
-  const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
-  const AxisTranspose<T, BCX> tx_(i, nx, gc.inv2dx, gc.invdx);
-  T satx = T(0);
-  if (BCX == BC_REFLECTING) {
-    if (i == 0) satx = T(-2.0 * gc.invdx);
-    if (i == nx - 1) satx = T(2.0 * gc.invdx);
-  }
-
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int lr = ty + k * THREAD_ROWS;
     const int j = j0 + lr;
     if (i >= nx || j >= ny) continue;
-    const AxisStencil<BCY> ay(j, ny, gc.inv2dy, gc.invdy);
-    const AxisTranspose<T, BCY> ty_(j, ny, gc.inv2dy, gc.invdy);
-    T saty = T(0);
-    if (BCY == BC_REFLECTING) {
-      if (j == 0) saty = T(-2.0 * gc.invdy);
-      if (j == ny - 1) saty = T(2.0 * gc.invdy);
-    }
-    const int r = lr + 1, c = tx + 1;
-    Node<T> nc, nxm, nxp, nym, nyp;
-    Seed<T> ac, axm, axp, aym, ayp;
-    vjp_lds(s, r, c, nc, ac);
-    vjp_lds(s, r, c - 1, nxm, axm);
-    vjp_lds(s, r, c + 1, nxp, axp);
-    vjp_lds(s, r - 1, c, nym, aym);
-    vjp_lds(s, r + 1, c, nyp, ayp);
-    // local part: reverse of this node's own rates (stencil neighbours with closures)
-    const Node<T>& sxm = ax.om == 0 ? nc : nxm;
-    const Node<T>& sxp = ax.op == 0 ? nc : nxp;
-    const Node<T>& sym = ay.om == 0 ? nc : nym;
-    const Node<T>& syp = ay.op == 0 ? nc : nyp;
-    const T kb[5] = {ac.h, ac.u, ac.v, ac.w, ac.eta};
-    Cot<T> out;
-    T dX[12], dY[12];
-    split_form_reverse<T>(nc, sxm, sxp, sym, syp, T(ax.scale), T(ay.scale), g, lam, satx, saty, kb, out, dX, dY);
-    // transpose part: Dbar of the neighbours (and of this node on closure columns)
-    T qa[12], qb[12], amt[12];
-    dbar_x(nxm, axm, g, lam, qa);
-    dbar_x(nxp, axp, g, lam, qb);
-#pragma unroll
-    for (int m = 0; m < 12; ++m) amt[m] = tx_.wl * qa[m] + tx_.wc * dX[m] + tx_.wr * qb[m];
-    out.add(chain_x(nc, amt));
-    dbar_y(nym, aym, g, lam, qa);
-    dbar_y(nyp, ayp, g, lam, qb);
-#pragma unroll
-    for (int m = 0; m < 12; ++m) amt[m] = ty_.wl * qa[m] + ty_.wc * dY[m] + ty_.wr * qb[m];
-    out.add(chain_y(nc, amt));
-
+    // this node's qbar and bbar, loaded before the evaluation so that their
+    // latency overlaps it (the sum Acc is read at the end: loaded here too it
+    // takes the reflecting instances past 256 registers)
     const size_t od = (size_t)j * nx + i;
+    T qv[5], bv = T(0);
+    if (ROLE != VJP_PLAIN) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qv[f] = Qb[f * N + od];
+      bv = Bb[od];
+    }
+    const Cot<T> out = vjp_node<T, BCX, BCY>(s, lr + 1, tx + 1, i, j, gc);
     const T yb[5] = {out.h, out.u, out.v, out.w, out.eta};
     if (ROLE == VJP_PLAIN) {
 #pragma unroll
@@ -455,23 +477,232 @@ __global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, 
       if (ROLE == VJP_S4) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          const T q = Qb[f * N + od];
-          Kout[f * N + od] = cq * q + cy * yb[f];
+          Kout[f * N + od] = cq * qv[f] + cy * yb[f];
           Acc[f * N + od] = yb[f];
         }
       } else if (ROLE == VJP_S3 || ROLE == VJP_S2) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
-          const T q = Qb[f * N + od];
-          Kout[f * N + od] = cq * q + cy * yb[f];
+          Kout[f * N + od] = cq * qv[f] + cy * yb[f];
           Acc[f * N + od] = Acc[f * N + od] + yb[f];
         }
       } else {
 #pragma unroll
-        for (int f = 0; f < 5; ++f) Qb[f * N + od] = Qb[f * N + od] + Acc[f * N + od] + yb[f];
+        for (int f = 0; f < 5; ++f) Qb[f * N + od] = qv[f] + Acc[f * N + od] + yb[f];
       }
-      Bb[od] = Bb[od] + out.b;
+      Bb[od] = bv + out.b;
     }
+  }
+}
+
+// Two consecutive reverse stages in one launch, the reverse counterpart of the
+// step kernel's temporal blocking: PAIR = 2 runs roles S4 and S3, PAIR = 1
+// roles S2 and S1, over the step kernel's TX x (512 / TX) tiles.  The first
+// evaluation (state YA and seed aA * KinA, staged with a two-node halo) runs
+// on the tile and on the ring of nodes around it; there its stage cotangent
+// YbarA gives the second evaluation's seed kbB = cqA qbar + cyA YbarA, which
+// replaces the first seed in LDS beside the second state YB (one-node halo),
+// and the second evaluation runs on the tile:
+//   PAIR 2: KinA = qbar, aA = dt/6, YA = Y4, YB = Y3, (cqA, cyA) = (dt/3, dt),
+//           Kout = cqB qbar + cyB YbarB with (cqB, cyB) = (dt/3, dt/2),
+//           Acc = YbarA + YbarB (YbarA written after the first evaluation)
+//   PAIR 1: KinA = the seed of S2, aA = 1, YA = Y2, YB = Y1 = q_n,
+//           (cqA, cyA) = (dt/6, dt/2), QbOut = qbar + (Acc + YbarA) + YbarB
+//           (a buffer other than Qb: neighbouring tiles still read qbar on
+//           their rings while this one writes)
+//   both:   bbar = (bbar + bbarA) + bbarB, the first sum written after the
+//           first evaluation.
+// Node by node this is the arithmetic of the two role kernels (the compiler
+// fuses the multiply-adds of the separately built kernels differently, so the
+// results agree to rounding), and the results do not depend on the tile
+// shape.  Algorithmic traffic per node: 28 values for S4 + S3
+// (role kernels: 56) and 33 for S2 + S1 (61), plus the sums written between
+// the evaluations and read back (6 values each way, mostly served by L2); the
+// price is the ring of first evaluations (1 + 2 (TX + 2 + TY) / 512 of them
+// per owned node).
+template <typename T, int TX>
+struct VjpPairSmem {
+  T f[12][StepGeom<TX>::TY + 4][TX + 4];  // h u v w eta b 1/h | seeds of h u v w eta
+};
+
+template <typename T, int BCX, int BCY, int PAIR, int TX>
+__global__ __launch_bounds__(STAGE_THREADS, 2) void vjp_pair_kernel(const GridConst gc, const T* __restrict__ YA,
+                                                                 const T* __restrict__ YB,
+                                                                 const T* __restrict__ bplane, const T* KinA,
+                                                                 const T* Qb, T* __restrict__ QbOut,
+                                                                 T* __restrict__ Kout, T* __restrict__ Acc,
+                                                                 T* __restrict__ Bb, T aA, T cqA, T cyA, T cqB,
+                                                                 T cyB) {
+  static_assert(PAIR == 1 || PAIR == 2, "PAIR is 2 (S4 + S3) or 1 (S2 + S1)");
+  using G = StepGeom<TX>;
+  constexpr int TY = G::TY;
+  constexpr int H = 2;  // LDS position of tile node (0, 0)
+  constexpr int RXA = TX + 2 * H, REGA = RXA * (TY + 2 * H);
+  constexpr int RXB = TX + 2, REGB = RXB * (TY + 2);
+  __shared__ VjpPairSmem<T, TX> s;
+  const int nx = gc.nx, ny = gc.ny;
+  const size_t N = (size_t)nx * (size_t)ny;
+  const int ntx = (nx + TX - 1) / TX;
+  const int nty = (ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  const int i0 = (tile % ntx) * TX;
+  const int j0 = (tile / ntx) * TY;
+  const int tid = threadIdx.x;
+
+  // 1. YA, b and aA * KinA with a two-node halo; all loads issued first
+  {
+    constexpr int ITER = (REGA + STAGE_THREADS - 1) / STAGE_THREADS;
+    T v[ITER][11];
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGA) {
+        const int rr = idx / RXA;
+        const int cc = idx - rr * RXA;
+        const size_t o = (size_t)wrap_or_clamp<BCY>(j0 - H + rr, ny) * nx + wrap_or_clamp<BCX>(i0 - H + cc, nx);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[it][f] = YA[f * N + o];
+        v[it][5] = bplane[o];
+#pragma unroll
+        for (int f = 0; f < 5; ++f) v[it][6 + f] = KinA[f * N + o];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < ITER; ++it) {
+      const int idx = tid + it * STAGE_THREADS;
+      if (idx < REGA) {
+        const int rr = idx / RXA;
+        const int cc = idx - rr * RXA;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
+        s.f[6][rr][cc] = recip_staged(v[it][0]);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = aA * v[it][6 + f];
+      }
+    }
+  }
+
+  // Slots of this thread: slot 0 the ring node tid (if any), slots 1 and 2 the
+  // tile nodes (lx, ly0) and (lx, ly0 + 1); positions relative to the tile.
+  const int lx = tid % TX;
+  const int ly0 = 2 * (tid / TX);
+  int pr[3], pc[3];
+  bool slot[3], ev[3];
+  slot[0] = tid < G::RING1;
+  pr[0] = 0;
+  pc[0] = 0;
+  if (slot[0]) ring_node<TX>(tid, pr[0], pc[0]);
+  pr[1] = ly0;
+  pc[1] = lx;
+  pr[2] = ly0 + 1;
+  pc[2] = lx;
+  slot[1] = slot[2] = true;
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+    ev[q] = slot[q] && on_axis<BCX>(i0 + pc[q], nx) && on_axis<BCY>(j0 + pr[q], ny);
+  __syncthreads();
+
+  // 2. First evaluation on the ring and the tile (periodic images of nodes
+  //    past a ragged edge included): the seeds of the second one.
+  //    The owned nodes' sums go to memory as the role kernels write them
+  //    (Acc, bbar; read back after the second evaluation, from L2).
+  T kbB[3][5];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (!ev[q]) continue;
+    const int iw = wrap_or_clamp<BCX>(i0 + pc[q], nx), jw = wrap_or_clamp<BCY>(j0 + pr[q], ny);
+    const size_t o = (size_t)jw * nx + iw;
+    const Cot<T> out = vjp_node<T, BCX, BCY>(s, pr[q] + H, pc[q] + H, iw, jw, gc);
+    const T yb[5] = {out.h, out.u, out.v, out.w, out.eta};
+#pragma unroll
+    for (int f = 0; f < 5; ++f) kbB[q][f] = cqA * Qb[f * N + o] + cyA * yb[f];
+    if (q > 0 && i0 + pc[q] < nx && j0 + pr[q] < ny) {
+      if (PAIR == 2) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) Acc[f * N + o] = yb[f];
+      } else {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) Acc[f * N + o] = Acc[f * N + o] + yb[f];
+      }
+      Bb[o] = Bb[o] + out.b;
+    }
+  }
+  // the second state, loaded while the other waves finish their evaluations
+  constexpr int ITB = (REGB + STAGE_THREADS - 1) / STAGE_THREADS;
+  T w[ITB][5];
+#pragma unroll
+  for (int it = 0; it < ITB; ++it) {
+    const int idx = tid + it * STAGE_THREADS;
+    if (idx < REGB) {
+      const int rr = idx / RXB;
+      const int cc = idx - rr * RXB;
+      const size_t o = (size_t)wrap_or_clamp<BCY>(j0 - 1 + rr, ny) * nx + wrap_or_clamp<BCX>(i0 - 1 + cc, nx);
+#pragma unroll
+      for (int f = 0; f < 5; ++f) w[it][f] = YB[f * N + o];
+    }
+  }
+  __syncthreads();
+
+  // 3. YB and its 1/h over the one-node halo (b stays), the new seeds on the
+  //    tile and ring.  Positions outside a reflecting wall then take the seed
+  //    of the wall node they copy, as the role kernels stage them.
+#pragma unroll
+  for (int it = 0; it < ITB; ++it) {
+    const int idx = tid + it * STAGE_THREADS;
+    if (idx < REGB) {
+      const int rr = idx / RXB + H - 1;
+      const int cc = idx - (idx / RXB) * RXB + H - 1;
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.f[f][rr][cc] = w[it][f];
+      s.f[6][rr][cc] = recip_staged(w[it][0]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (!ev[q]) continue;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) s.f[7 + f][pr[q] + H][pc[q] + H] = kbB[q][f];
+  }
+  if (BCX == BC_REFLECTING || BCY == BC_REFLECTING) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (!slot[q] || ev[q]) continue;
+      // the reflecting axis clamps; on a periodic axis the position is its own
+      const int ic = BCX == BC_REFLECTING ? wrap_or_clamp<BC_REFLECTING>(i0 + pc[q], nx) - i0 : pc[q];
+      const int jc = BCY == BC_REFLECTING ? wrap_or_clamp<BC_REFLECTING>(j0 + pr[q], ny) - j0 : pr[q];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) s.f[7 + f][pr[q] + H][pc[q] + H] = s.f[7 + f][jc + H][ic + H];
+    }
+  }
+  __syncthreads();
+
+  // 4. Second evaluation on the owned nodes in the domain, and the outputs.
+  const int i = i0 + lx;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    __builtin_amdgcn_sched_barrier(0);
+    const int j = j0 + ly0 + k;
+    if (i >= nx || j >= ny) continue;
+    const size_t od = (size_t)j * nx + i;
+    T qv[5];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) qv[f] = Qb[f * N + od];
+    const T bv = Bb[od];
+    const Cot<T> out = vjp_node<T, BCX, BCY>(s, ly0 + k + H, lx + H, i, j, gc);
+    const T yb[5] = {out.h, out.u, out.v, out.w, out.eta};
+    if (PAIR == 2) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        Kout[f * N + od] = cqB * qv[f] + cyB * yb[f];
+        Acc[f * N + od] = Acc[f * N + od] + yb[f];
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) QbOut[f * N + od] = qv[f] + Acc[f * N + od] + yb[f];
+    }
+    Bb[od] = bv + out.b;
   }
 }
 

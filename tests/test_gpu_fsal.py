@@ -8,7 +8,9 @@ norms within 1e-10 relative (they differ only by rounding, which the
 controller's powers pass on), and the final state within 1e-12 field-relative
 (FP64).  Fixed-step runs (every step accepted) are compared the same way, on
 both boundary types and both tile heights, and FP32 runs against the FP32
-bound of the plain step."""
+bound of the plain step.  Every case runs on the default step path (the middle
+four evaluations of an attempt in one launch of the step tile) and on the
+four-stage path (one role kernel per evaluation); the two give the same bits."""
 
 import numpy as np
 import pytest
@@ -35,10 +37,14 @@ def compare_records(got, ref):
     np.testing.assert_allclose(got[:, 1], ref[:, 1], rtol=1e-10, atol=1e-12)
 
 
-def run_gpu(g, q0, b, t_end, dt0, dtype=torch.float64, ty=None, **kw):
+PATHS = ["fused", "stages"]
+
+
+def run_gpu(g, q0, b, t_end, dt0, dtype=torch.float64, ty=None, path="fused", **kw):
     s = solver(g, dtype)
     if ty is not None:
         s.set_tile_y(ty)
+    s.set_step_path(path)
     s.set_bathymetry(dev(b, dtype))
     qd = dev(q0, dtype)
     res, rec = s.step_adaptive(qd, 0.0, t_end, dt0, record=4096, **kw)
@@ -47,24 +53,26 @@ def run_gpu(g, q0, b, t_end, dt0, dtype=torch.float64, ty=None, **kw):
     return res, rec, host(qd)
 
 
-@pytest.mark.parametrize("bc", [PER, REF])
-def test_adaptive_run_matches_oracle(bc):
-    """rtol = atol = 1e-6 (the paper's tolerances) on a 64^2 Gaussian bump
-    (periodic, lambda = 500) and on a wavy reflecting state."""
+def adaptive_case(bc):
+    """A 64^2 Gaussian bump (periodic, lambda = 500) or a wavy reflecting state."""
     if bc == PER:
         p = W.gaussian_bump_periodic(64, seed=1)
         g, b = p.grid, p.b
-        q0 = oracle.init_aux(g, p.q0, b)
-        t_end = 1.0
-    else:
-        g = W.Grid(96, 40, 0.0, 30.0, 0.0, 10.0, REF, REF, 9.81, 500.0)
-        q, b = W.random_state(g, 11, b_scale=0.05)
-        q[1:4] *= 0.05
-        q0 = oracle.init_aux(g, q, b)
-        t_end = 0.2
+        return g, oracle.init_aux(g, p.q0, b), b, 1.0
+    g = W.Grid(96, 40, 0.0, 30.0, 0.0, 10.0, REF, REF, 9.81, 500.0)
+    q, b = W.random_state(g, 11, b_scale=0.05)
+    q[1:4] *= 0.05
+    return g, oracle.init_aux(g, q, b), b, 0.2
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_adaptive_run_matches_oracle(bc, path):
+    """rtol = atol = 1e-6 (the paper's tolerances)."""
+    g, q0, b, t_end = adaptive_case(bc)
     dt0 = oracle.cfl_dt(g, q0, 0.5)
     ref, t_ref, na, nr, rec_ref = oracle.fsal35(g, q0, b, 0.0, t_end, dt0)
-    res, rec, got = run_gpu(g, q0, b, t_end, dt0)
+    res, rec, got = run_gpu(g, q0, b, t_end, dt0, path=path)
     assert res["reached_end"] == 1 and res["t"] == t_ref == t_end
     assert (res["accepted"], res["rejected"]) == (na, nr)
     compare_records(rec, rec_ref)
@@ -72,7 +80,23 @@ def test_adaptive_run_matches_oracle(bc):
     assert np.all(err <= F64_TOL), err
 
 
-def test_too_large_first_step_is_rejected_like_the_oracle():
+@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_fused_attempt_matches_role_kernels_bitwise(bc, ty):
+    """The one-launch middle evaluations and the four role kernels do the same
+    arithmetic node by node: same records, same final state, bit for bit (both
+    tile shapes of the step tile: 64 x 8 and 32 x 16)."""
+    g, q0, b, t_end = adaptive_case(bc)
+    dt0 = oracle.cfl_dt(g, q0, 0.5)
+    out = [run_gpu(g, q0, b, t_end, dt0, ty=ty, path=path) for path in PATHS]
+    (r0, rec0, q0f), (r1, rec1, q1f) = out
+    assert r0 == r1
+    assert np.array_equal(rec0, rec1)
+    assert np.array_equal(q0f, q1f)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_too_large_first_step_is_rejected_like_the_oracle(path):
     p = W.gaussian_bump_periodic(64, seed=2)
     g, b = p.grid, p.b
     q0 = oracle.init_aux(g, p.q0, b)
@@ -80,14 +104,15 @@ def test_too_large_first_step_is_rejected_like_the_oracle():
     t_end = 30 * dt_cfl
     ref, t_ref, na, nr, rec_ref = oracle.fsal35(g, q0, b, 0.0, t_end, 15 * dt_cfl)
     assert nr >= 1
-    res, rec, got = run_gpu(g, q0, b, t_end, 15 * dt_cfl)
+    res, rec, got = run_gpu(g, q0, b, t_end, 15 * dt_cfl, path=path)
     compare_records(rec, rec_ref)
     assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("ty", [8, 16])
-@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF)])
-def test_fixed_steps_match_oracle(bcs, ty):
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
+def test_fixed_steps_match_oracle(bcs, ty, path):
     """Fixed steps (adaptive = 0) on a ragged grid: the state after 7 steps and
     the recorded error norms."""
     g = W.Grid(70, 37, -1.0, 2.0, 0.5, 2.0, bcs[0], bcs[1], 9.81, 500.0)
@@ -96,13 +121,14 @@ def test_fixed_steps_match_oracle(bcs, ty):
     q0 = oracle.init_aux(g, q, b)
     dt = 0.3 * oracle.cfl_dt(g, q0, 0.5)
     ref, _, na, _, rec_ref = oracle.fsal35(g, q0, b, 0.0, 7 * dt, dt, adaptive=False)
-    res, rec, got = run_gpu(g, q0, b, 7 * dt, dt, ty=ty, adaptive=False)
+    res, rec, got = run_gpu(g, q0, b, 7 * dt, dt, ty=ty, path=path, adaptive=False)
     assert res["accepted"] == na == 7 and res["rejected"] == 0
     compare_records(rec, rec_ref)
     assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
 
 
-def test_fp32_bounded_by_oracle_fp32_error():
+@pytest.mark.parametrize("path", PATHS)
+def test_fp32_bounded_by_oracle_fp32_error(path):
     """FP32 storage and arithmetic, fixed steps: within the FP32 bound of the
     plain RK4 step over the same interval (the pair's rounding is of the same
     kind), against the FP64 oracle pair."""
@@ -114,7 +140,7 @@ def test_fp32_bounded_by_oracle_fp32_error():
     ref, *_ = oracle.fsal35(g, q0, b32, 0.0, 20 * dt, dt, adaptive=False)
     bound = field_rel_err(oracle.rk4_f32(g, q0, b32, dt, 20).astype(np.float64), oracle.rk4(g, q0, b32, dt, 20),
                           STATE_FLOORS)
-    res, rec, got = run_gpu(g, q0, b32, 20 * dt, dt, dtype=torch.float32, adaptive=False)
+    res, rec, got = run_gpu(g, q0, b32, 20 * dt, dt, dtype=torch.float32, path=path, adaptive=False)
     assert res["accepted"] == 20
     err = field_rel_err(got, ref, STATE_FLOORS)
     assert np.all(err <= fp32_bound(bound)), (err, bound)
@@ -140,3 +166,29 @@ def test_attempt_limit_and_arguments():
     with pytest.raises(SgnError) as ei:
         src.step_adaptive(dev(np.ones((5, 32, 32))), 0.0, 1.0, 1e-3)
     assert ei.value.status == -3
+
+
+@pytest.fixture(scope="module")
+def obstacle_full_size():
+    """The paper's solitary wave over a Gaussian obstacle at its spacing 0.025
+    (1600 x 800, periodic) from t = 0 to 0.03 at rtol = atol = 1e-6 (the
+    first attempts of the adaptive benchmark run, step growing from the CFL
+    step), on the oracle's threaded build (bit-identical to the serial one)."""
+    p = W.gaussian_obstacle(1600)
+    g, b = p.grid, p.b
+    with oracle.threaded():
+        q0 = oracle.init_aux(g, p.q0, b)
+        dt0 = oracle.cfl_dt(g, q0, 0.5)
+        ref, t_ref, na, nr, rec_ref = oracle.fsal35(g, q0, b, 0.0, 0.03, dt0)
+    return g, q0, b, dt0, ref, t_ref, na, nr, rec_ref
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_full_size_obstacle_run_matches_oracle(obstacle_full_size, path):
+    g, q0, b, dt0, ref, t_ref, na, nr, rec_ref = obstacle_full_size
+    assert na >= 6
+    res, rec, got = run_gpu(g, q0, b, 0.03, dt0, path=path)
+    assert res["reached_end"] == 1 and res["t"] == t_ref
+    assert (res["accepted"], res["rejected"]) == (na, nr)
+    compare_records(rec, rec_ref)
+    assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
