@@ -541,7 +541,31 @@ def run_adaptive(nx, t_end, label, rtol=1e-6, atol=1e-6):
         f"(mean step {out['mean_step']:.3e}, CFL step {dt_cfl:.3e}) in {wall:.3f} s; "
         f"RK4 at the CFL step: {n_rk4} steps in {wall_rk4:.3f} s; role kernels: {wall_roles:.3f} s "
         f"(same bits: {same_bits})")
+    # The same run in FP32 storage and arithmetic (error norm and controller in FP64 on the device): the
+    # paper ran everything in FP64 after adaptive stepping misbehaved in FP32 in its implementation.
+    qh = q.double().cpu()
     s.close()
+    del q, qr, q0
+    torch.cuda.empty_cache()
+    s32 = Solver(g, torch.float32)
+    q32 = torch.from_numpy(p.q0).float().cuda()
+    s32.set_bathymetry(torch.from_numpy(p.b).float().cuda())
+    s32.init_aux(q32)
+    dt32 = s32.cfl_dt(q32, 0.5)
+    q32_0 = q32.clone()
+    s32.step_adaptive(q32, 0.0, 4 * dt32, dt32, rtol, atol)
+    q32.copy_(q32_0)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    res32 = s32.step_adaptive(q32, 0.0, t_end, dt32, rtol, atol)
+    wall32 = time.perf_counter() - t3
+    out["fp32"] = {"accepted": res32["accepted"], "rejected": res32["rejected"], "t": res32["t"],
+                   "mean_step": t_end / max(res32["accepted"], 1), "wall_s": wall32,
+                   "ms_per_attempt": wall32 / res32["attempts"] * 1e3, "last_err": res32["last_err"],
+                   "max_abs_h_diff_vs_fp64": float(torch.max(torch.abs(q32[0].double().cpu() - qh[0])))}
+    log(f"[{label} fp32] {res32['accepted']} accepted / {res32['rejected']} rejected steps in {wall32:.3f} s; "
+        f"max |h - h_fp64| {out['fp32']['max_abs_h_diff_vs_fp64']:.2e}")
+    s32.close()
     torch.cuda.empty_cache()
     return out
 
