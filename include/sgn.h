@@ -291,7 +291,9 @@ sgn_status sgn_rhs_vjp(sgn_ctx* ctx, const void* q, const void* a, void* qbar, v
  * cotangent of q_{n+1}; on exit the cotangent of q_n.  bbar accumulates (+=)
  * the bathymetry cotangent.  The stage states are recomputed (by the pair
  * kernels on SGN_PATH_PAIRS, by the step kernel otherwise; the same values
- * either way) and reversed in the order k4, k3, k2, k1. */
+ * either way) and reversed in the order k4, k3, k2, k1: on SGN_PATH_FUSED
+ * (default) two stages per launch (k4 with k3, k2 with k1), on the other
+ * paths one stage per launch; the two forms agree to rounding. */
 sgn_status sgn_step_vjp(sgn_ctx* ctx, const void* q_n, double dt, void* qbar, void* bbar);
 
 /* Gauge series of a rollout: from the initial surface zeta0 (device plane),
@@ -310,8 +312,9 @@ sgn_status sgn_gauge_series(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, dou
  * checkpoint_every steps (0: ceil(sqrt(nsteps))); the reverse sweep
  * recomputes one segment at a time, keeping its states and stage states, and
  * runs the step VJPs backwards.  The forward steps follow the context's step
- * path (pair kernels on SGN_PATH_PAIRS, the step kernel otherwise).  Memory:
- * checkpoints plus 4*K+1 states for a segment of K steps.  *loss is a host
+ * path (pair kernels on SGN_PATH_PAIRS, the step kernel otherwise), and so do
+ * the step VJPs (as in sgn_step_vjp).  Memory: checkpoints plus 4*K+1 states
+ * for a segment of K steps, plus five states of cotangent work buffers.  *loss is a host
  * double.  Synchronizes. */
 sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
                                int32_t ngauges, const double* target, int64_t checkpoint_every, double* loss,
