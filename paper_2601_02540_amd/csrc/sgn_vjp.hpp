@@ -287,8 +287,10 @@ struct VjpSmem {
   T f[12][TY + 2][TILE_X + 2];  // h u v w eta b 1/h | seeds of h u v w eta
 };
 
-template <typename T, class Smem>
-__device__ __forceinline__ void vjp_lds(const Smem& s, int r, int c, Node<T>& n, Seed<T>& a) {
+// With SCALE, the seed planes hold unscaled values and the seeds are formed as
+// sc * plane here (the same product the role kernels store when staging).
+template <typename T, bool SCALE = false, class Smem>
+__device__ __forceinline__ void vjp_lds(const Smem& s, int r, int c, Node<T>& n, Seed<T>& a, T sc = T(1)) {
   n.h = s.f[0][r][c];
   n.u = s.f[1][r][c];
   n.v = s.f[2][r][c];
@@ -296,19 +298,20 @@ __device__ __forceinline__ void vjp_lds(const Smem& s, int r, int c, Node<T>& n,
   n.eta = s.f[4][r][c];
   n.b = s.f[5][r][c];
   n.ih = s.f[6][r][c];
-  a.h = s.f[7][r][c];
-  a.u = s.f[8][r][c];
-  a.v = s.f[9][r][c];
-  a.w = s.f[10][r][c];
-  a.eta = s.f[11][r][c];
+  a.h = SCALE ? sc * s.f[7][r][c] : s.f[7][r][c];
+  a.u = SCALE ? sc * s.f[8][r][c] : s.f[8][r][c];
+  a.v = SCALE ? sc * s.f[9][r][c] : s.f[9][r][c];
+  a.w = SCALE ? sc * s.f[10][r][c] : s.f[10][r][c];
+  a.eta = SCALE ? sc * s.f[11][r][c] : s.f[11][r][c];
 }
 
 // Cotangent of the raw values of node (i, j), in the domain: the reverse of
 // its own rates plus what its neighbours' derivatives send it (the gathered
 // transpose), from a staging s that holds Y, b, 1/h and the seeds (planes
 // 0..11) around the node's position (r, c).
-template <typename T, int BCX, int BCY, class Smem>
-__device__ __forceinline__ Cot<T> vjp_node(const Smem& s, int r, int c, int i, int j, const GridConst& gc) {
+template <typename T, int BCX, int BCY, bool SCALE = false, class Smem>
+__device__ __forceinline__ Cot<T> vjp_node(const Smem& s, int r, int c, int i, int j, const GridConst& gc,
+                                           T sc = T(1)) {
   const int nx = gc.nx, ny = gc.ny;
   const T g = T(gc.g), lam = T(gc.lam);
   const AxisStencil<BCX> ax(i, nx, gc.inv2dx, gc.invdx);
@@ -327,11 +330,11 @@ __device__ __forceinline__ Cot<T> vjp_node(const Smem& s, int r, int c, int i, i
   }
   Node<T> nc, nxm, nxp, nym, nyp;
   Seed<T> ac, axm, axp, aym, ayp;
-  vjp_lds(s, r, c, nc, ac);
-  vjp_lds(s, r, c - 1, nxm, axm);
-  vjp_lds(s, r, c + 1, nxp, axp);
-  vjp_lds(s, r - 1, c, nym, aym);
-  vjp_lds(s, r + 1, c, nyp, ayp);
+  vjp_lds<T, SCALE>(s, r, c, nc, ac, sc);
+  vjp_lds<T, SCALE>(s, r, c - 1, nxm, axm, sc);
+  vjp_lds<T, SCALE>(s, r, c + 1, nxp, axp, sc);
+  vjp_lds<T, SCALE>(s, r - 1, c, nym, aym, sc);
+  vjp_lds<T, SCALE>(s, r + 1, c, nyp, ayp, sc);
   // Opaque copies: where one thread evaluates neighbouring nodes, the compiler
   // would otherwise share loads and products between the evaluations and fuse
   // the arithmetic differently; every evaluation rounds as a lone one does.
@@ -503,7 +506,9 @@ __global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, 
 // YbarA gives the second evaluation's seed kbB = cqA qbar + cyA YbarA, which
 // replaces the first seed in LDS beside the second state YB (one-node halo),
 // and the second evaluation runs on the tile:
-//   PAIR 2: KinA = qbar, aA = dt/6, YA = Y4, YB = Y3, (cqA, cyA) = (dt/3, dt),
+//   PAIR 2: KinA = qbar, aA = dt/6 (the seed planes hold qbar itself and the
+//           seeds aA qbar are formed as they are read, so kbB takes qbar from
+//           LDS), YA = Y4, YB = Y3, (cqA, cyA) = (dt/3, dt),
 //           Kout = cqB qbar + cyB YbarB with (cqB, cyB) = (dt/3, dt/2),
 //           Acc = YbarA + YbarB (YbarA written after the first evaluation)
 //   PAIR 1: KinA = the seed of S2, aA = 1, YA = Y2, YB = Y1 = q_n,
@@ -577,7 +582,7 @@ __global__ __launch_bounds__(STAGE_THREADS, 2) void vjp_pair_kernel(const GridCo
         for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
         s.f[6][rr][cc] = recip_staged(v[it][0]);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = aA * v[it][6 + f];
+        for (int f = 0; f < 5; ++f) s.f[7 + f][rr][cc] = PAIR == 2 ? v[it][6 + f] : aA * v[it][6 + f];
       }
     }
   }
@@ -613,10 +618,12 @@ __global__ __launch_bounds__(STAGE_THREADS, 2) void vjp_pair_kernel(const GridCo
     if (!ev[q]) continue;
     const int iw = wrap_or_clamp<BCX>(i0 + pc[q], nx), jw = wrap_or_clamp<BCY>(j0 + pr[q], ny);
     const size_t o = (size_t)jw * nx + iw;
-    const Cot<T> out = vjp_node<T, BCX, BCY>(s, pr[q] + H, pc[q] + H, iw, jw, gc);
+    // PAIR 2: the seed planes hold qbar itself (KinA = qbar), scaled by aA as it is read
+    const Cot<T> out = vjp_node<T, BCX, BCY, PAIR == 2>(s, pr[q] + H, pc[q] + H, iw, jw, gc, aA);
     const T yb[5] = {out.h, out.u, out.v, out.w, out.eta};
 #pragma unroll
-    for (int f = 0; f < 5; ++f) kbB[q][f] = cqA * Qb[f * N + o] + cyA * yb[f];
+    for (int f = 0; f < 5; ++f)
+      kbB[q][f] = cqA * (PAIR == 2 ? s.f[7 + f][pr[q] + H][pc[q] + H] : Qb[f * N + o]) + cyA * yb[f];
     if (q > 0 && i0 + pc[q] < nx && j0 + pr[q] < ny) {
       if (PAIR == 2) {
 #pragma unroll
