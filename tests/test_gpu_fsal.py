@@ -95,6 +95,29 @@ def test_fused_attempt_matches_role_kernels_bitwise(bc, ty):
     assert np.array_equal(q0f, q1f)
 
 
+def test_switching_paths_on_one_context():
+    """One context alternating between the step paths and tile shapes: each
+    change drops the captured attempts, and every run gives the first run's
+    bits."""
+    g, q0, b, t_end = adaptive_case(PER)
+    dt0 = oracle.cfl_dt(g, q0, 0.5)
+    s = solver(g)
+    s.set_bathymetry(dev(b))
+    qd = dev(q0)
+    q0d = qd.clone()
+    outs = []
+    # the same state buffer and no record every time: only the path and the tiles tell the runs apart
+    for path, ty in (("fused", 16), ("stages", 16), ("fused", 8), ("pairs", 8), ("fused", 16)):
+        s.set_tile_y(ty)
+        s.set_step_path(path)
+        qd.copy_(q0d)
+        res = s.step_adaptive(qd, 0.0, t_end, dt0)
+        outs.append((res, host(qd)))
+    for res, q in outs[1:]:
+        assert res == outs[0][0]
+        assert np.array_equal(q, outs[0][1])
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_too_large_first_step_is_rejected_like_the_oracle(path):
     p = W.gaussian_bump_periodic(64, seed=2)
@@ -144,6 +167,29 @@ def test_fp32_bounded_by_oracle_fp32_error(path):
     assert res["accepted"] == 20
     err = field_rel_err(got, ref, STATE_FLOORS)
     assert np.all(err <= fp32_bound(bound)), (err, bound)
+
+
+def test_fp32_adaptive_run_reaches_the_fp64_solution():
+    """Adaptive stepping with FP32 state and arithmetic (error norm and
+    controller in FP64) at the paper's tolerances, 64^2 Gaussian bump to t = 1
+    (the paper left FP32 after step-size trouble with adaptive stepping): the
+    run reaches t_end, rejects few attempts (here as many as the FP64 run: 2 of
+    31), takes within 30% of the FP64 oracle run's accepted steps, and ends
+    within 1e-4 field-relative of the oracle's state: about 30 steps each
+    allowed a local error of 1e-6 relative, plus the FP32 rounding of the
+    state (measured: at most 8e-6)."""
+    p = W.gaussian_bump_periodic(64, seed=1)
+    g = p.grid
+    b32 = p.b.astype(np.float32).astype(np.float64)
+    q0 = oracle.init_aux(g, p.q0, b32)
+    dt0 = oracle.cfl_dt(g, q0, 0.5)
+    ref, t_ref, na, nr, _ = oracle.fsal35(g, q0, b32, 0.0, 1.0, dt0)
+    res, rec, got = run_gpu(g, q0.astype(np.float32).astype(np.float64), b32, 1.0, dt0, dtype=torch.float32)
+    err = field_rel_err(got, ref, STATE_FLOORS)
+    print("fp32 adaptive:", res, "fp64 accepted/rejected", na, nr, "field errors", err)
+    assert res["reached_end"] == 1 and res["rejected"] <= 0.1 * res["attempts"], res
+    assert abs(res["accepted"] - na) <= 0.3 * na, (res["accepted"], na)
+    assert np.all(err <= 1e-4), err
 
 
 def test_attempt_limit_and_arguments():
