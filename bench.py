@@ -66,10 +66,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
 # they had when the counters were taken.
-STEP_TRAFFIC_BYTES_PER_NODE = (1184915927.0 + 671088640.0) / 16777216
+STEP_TRAFFIC_BYTES_PER_NODE = (1190166094.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "77fbc46cfeeaf6dd9665b98784f6478a7a2f6da5f87d337f4ddc0662cff3df1a"
+STEP_SOURCES_SHA256 = "cb0c3833c4f59014d1f8685784ceb695f8b95d74502abdb0c21ddd4f5caef378"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

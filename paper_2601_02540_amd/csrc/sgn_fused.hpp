@@ -163,6 +163,10 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
     T v[ITER][6];
     T kst[RK == RK_FSAL ? ITER : 1][5];
+    // The staging waves take the issue priority until the barrier: their loads
+    // and LDS writes go out ahead of the other workgroup's evaluation on the
+    // same SIMDs (measured: FP32 2% and FP64 0.3-0.5% faster, same bits).
+    __builtin_amdgcn_s_setprio(3);
 #pragma unroll
     for (int it = 0; it < ITER; ++it) {
       const int idx = tid + it * STAGE_THREADS;
@@ -229,6 +233,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     }
   }
 
+  __builtin_amdgcn_s_setprio(0);
   // Owned nodes (lx, ly0 + k), k = 0, 1, and ring slots of this thread.
   const int lx = tid % TX;
   const int ly0 = 2 * (tid / TX);
