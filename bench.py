@@ -146,10 +146,10 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, rep
         secs.append(t_start.elapsed_time(t_end) / 1e3)
         t += steps * dt
     sec = float(np.median(secs))
-    # per-launch durations of the path's kernels (direct launches with HIP events between them),
-    # after an unrecorded pass of 24 steps: the GPU runs the first ~20 launches after an idle spell
-    # up to 30% slower while its clocks settle
-    s.profile_stages(q, dt, 24)
+    # per-launch durations of the path's kernels (direct launches, events bound to the step kernel or
+    # between the kernels of the other paths), after an unrecorded pass of 64 steps: after an idle spell
+    # of a few tens of ms the GPU runs the next ~30 launches up to 30% slower while its clocks settle
+    s.profile_stages(q, dt, 64)
     ms = s.profile_stages(q, dt, 16)
     s.check()
     m1, e1 = s.mass_energy(q)

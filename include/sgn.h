@@ -263,8 +263,9 @@ sgn_status sgn_cfl_dt(sgn_ctx* ctx, const void* q, double cfl, double* dt);
  * the first wait, so the kernels run back to back).  Four-stage path: an event
  * between consecutive kernels, ms[s] = mean duration of stage kernel s (0 =
  * first, 1 and 2 = middle, 3 = last).  Pair path: likewise, ms[0] = pair 1,
- * ms[1] = pair 2, ms[2] = ms[3] = 0.  Fused path (one kernel per step): events
- * only around the measured launches, ms[0] = the step kernel, ms[1..3] = 0.  On
+ * ms[1] = pair 2, ms[2] = ms[3] = 0.  Fused path (one kernel per step): a start
+ * and a stop event bound to each step kernel's own execution, nothing enqueued
+ * between the launches; ms[0] = the step kernel, ms[1..3] = 0.  On
  * the pair and fused paths an odd nsteps is rounded up; the means leave out
  * the first step (two on those paths) when there are more.  nsteps <= 1024
  * (SGN_E_ARG otherwise).  Milliseconds; synchronizes. */

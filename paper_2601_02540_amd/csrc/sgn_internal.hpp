@@ -81,6 +81,9 @@ struct sgn_ctx {
   double* totals_series = nullptr;    // the series pointer captured in totals_graph
   sgn_host::AdjointBuffers adj;
   sgn_host::FsalBuffers fs;
+  // Set only inside sgn_profile_stages: the step kernel is then launched with
+  // these events bound to its own start and end.
+  hipEvent_t prof_start = nullptr, prof_stop = nullptr;
   std::string err;
 };
 

@@ -1,4 +1,5 @@
 // sgn_lib.hip -- C ABI of include/sgn.h: context, validation, launches, graphs.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -169,8 +170,15 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
   T* op = (T*)qout;
   T* ys = (T*)ysave;
 #define SGN_LAUNCH_K(BX, BY, S, SV, RX)                                                                         \
-  hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,       \
-                     (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys, rpart)
+  do {                                                                                                         \
+    if (c->prof_start)                                                                                         \
+      hipExtLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->prof_start,    \
+                            c->prof_stop, 0, c->gc, qp, bp, op, (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0),  \
+                            (T)dt, t0, dt, c->flag, ys, rpart);                                               \
+    else                                                                                                       \
+      hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,   \
+                         (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys, rpart);     \
+  } while (0)
 #define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false, sgn::EPI_NONE)
   const int bx = c->p.bc_x, by = c->p.bc_y;
   if (rpart && epi == sgn::EPI_RELAX) {  // relaxation sums (no source terms, no stage saving)
@@ -697,11 +705,13 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if ((pairs || fused) && (nsteps & 1)) ++nsteps;  // whole double steps, so the state ends in q
   const int nk = fused ? 0 : 4;                      // events between the launches of a profiled unit
   const int64_t units = (pairs || fused) ? nsteps / 2 : nsteps;
-  // One event between consecutive launches (fused path: one kernel per step,
-  // so only around the launches), all enqueued before the first wait, so the
-  // kernels run back to back as in a timed run; with more than one unit the
-  // first (warm-up) unit is left out of the means.
-  std::vector<hipEvent_t> ev(fused ? 3 : (size_t)(units * nk + 1), nullptr);
+  // Pair and four-stage paths: one event between consecutive launches.  Fused
+  // path: a start and a stop event bound to each step kernel itself
+  // (hipExtLaunchKernelGGL), so nothing is enqueued between the launches.  All
+  // launches go in before the first wait, so the kernels run back to back as in
+  // a timed run; with more than one unit the first (warm-up) unit is left out
+  // of the means.
+  std::vector<hipEvent_t> ev(fused ? (size_t)(4 * units + 1) : (size_t)(units * nk + 1), nullptr);
   hipError_t e = hipSuccess;
   for (auto& x : ev)
     if (!e) e = hipEventCreate(&x);
@@ -710,10 +720,15 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   for (int64_t u = 0; u < units && e == hipSuccess; ++u) {
     const double t = (double)u * ((pairs || fused) ? 2.0 : 1.0) * dt;
     if (fused) {
-      // two consecutive steps (q -> acc -> q); an event after the first unit and after the last
+      // two consecutive steps (q -> acc -> q), each timed by its own events
+      c->prof_start = ev[(size_t)(4 * u + 1)];
+      c->prof_stop = ev[(size_t)(4 * u + 2)];
       e = launch_fused(c, c->stream, q, c->acc, dt, t);
+      c->prof_start = ev[(size_t)(4 * u + 3)];
+      c->prof_stop = ev[(size_t)(4 * u + 4)];
       if (!e) e = launch_fused(c, c->stream, c->acc, q, dt, t + dt);
-      if (!e && (u == 0 || u == units - 1) && n < 3) e = hipEventRecord(ev[n++], c->stream);
+      c->prof_start = c->prof_stop = nullptr;
+      n = (int)(4 * u + 5);
     } else if (pairs) {
       // pair 1 and pair 2 of two consecutive steps (q -> acc -> q)
       e = launch_pair<1>(c, c->stream, q, nullptr, c->acc, c->yb, dt / 6.0, dt / 2.0, dt / 3.0, dt / 2.0, t, t + dt / 2.0);
@@ -738,11 +753,12 @@ sgn_status sgn_profile_stages(sgn_ctx* c, void* q, double dt, int64_t nsteps, do
   if (!e) e = hipEventSynchronize(ev[n - 1]);
   double acc_ms[4] = {0, 0, 0, 0};
   const int64_t first = units > 1 ? 1 : 0;
-  if (fused && !e) {
-    float m = 0.f;
-    e = hipEventElapsedTime(&m, ev[first], ev[first + 1]);  // units first .. units-1
-    acc_ms[0] = m;
-  }
+  for (int64_t u = first; u < units && !e && fused; ++u)
+    for (int k = 0; k < 2 && !e; ++k) {
+      float m = 0.f;
+      e = hipEventElapsedTime(&m, ev[(size_t)(4 * u + 1 + 2 * k)], ev[(size_t)(4 * u + 2 + 2 * k)]);
+      acc_ms[0] += m;
+    }
   for (int64_t u = first; u < units && !e && !fused; ++u)
     for (int k = 0; k < nk && !e; ++k) {
       float m = 0.f;
