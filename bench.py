@@ -74,7 +74,7 @@ KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
 ALL_VARIANTS = {"f32", "reflecting", "ensemble", "small", "adjoint", "paths", "paper", "relaxation", "totals",
-                "adaptive"}
+                "adaptive", "longdrift"}
 
 
 def log(msg):
@@ -475,6 +475,36 @@ def run_totals(problem, steps, warmup, tile_y):
     return res
 
 
+def run_long_drift(problem, nsteps=1000):
+    """The 4096^2 workload's whole 1000-step run in FP64 and in FP32 storage,
+    mass and energy recorded after every step by the step kernel: relative
+    drifts after 100, 500 and 1000 steps and the largest along the run."""
+    import torch
+    from paper_2601_02540_amd.binding import Solver
+    out = {}
+    for dtype, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        s = Solver(problem.grid, dtype)
+        b = torch.from_numpy(problem.b).to(dtype).cuda()
+        q = torch.from_numpy(problem.q0).to(dtype).cuda()
+        s.set_bathymetry(b)
+        s.init_aux(q)
+        dt = s.cfl_dt(q, 0.5)
+        m0, e0 = s.mass_energy(q)
+        series = s.step_totals(q, dt, nsteps).cpu().numpy()
+        dm = (series[:, 0] - m0) / abs(m0)
+        de = (series[:, 1] - e0) / abs(e0)
+        out[name] = {"steps": nsteps, "dt": dt,
+                     "energy_drift_rel": {str(n): float(de[n - 1]) for n in (100, 500, nsteps)},
+                     "mass_drift_rel": {str(n): float(dm[n - 1]) for n in (100, 500, nsteps)},
+                     "max_abs_energy_drift_rel": float(abs(de).max()), "max_abs_mass_drift_rel": float(abs(dm).max())}
+        log(f"[long run {name}] {nsteps} steps: energy drift {de[-1]:.3e} (max {abs(de).max():.3e}), "
+            f"mass drift {dm[-1]:.3e}")
+        s.close()
+        del q, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def run_adaptive(nx, t_end, label, rtol=1e-6, atol=1e-6):
     """The adaptive five-stage FSAL pair at the paper's tolerances on the paper's
     Gaussian-obstacle setup (nx x nx/2, spacing 40/nx), from t = 0 to t_end,
@@ -751,7 +781,7 @@ def main():
                     help="tile height (default: the library's per-dtype default)")
     ap.add_argument("--variants", default="all",
                     help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation,"
-                         "totals,adaptive (default all)")
+                         "totals,adaptive,longdrift (default all)")
     ap.add_argument("--ensemble-steps", type=int, default=100)
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--calib-copy", type=int, default=0, help="also copy this many bytes (counter calibration)")
@@ -826,6 +856,8 @@ def main():
         variants["recorded_totals_f64"] = run_totals(prob, min(args.steps, 200), 8, T)
     if "adaptive" in chosen:
         variants["adaptive_fsal_gaussian_obstacle_1600x800"] = run_adaptive(1600, 0.5, "adaptive pair 1600x800")
+    if "longdrift" in chosen and n == 4096:
+        variants["long_run_1000_steps_4096"] = run_long_drift(prob, 1000)
     if "paper" in chosen:
         variants["paper_setups"] = run_paper_setups(P, T)
     if args.long_dam_break:
