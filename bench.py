@@ -65,11 +65,13 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
 # 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
 # node and launch.  Reported only while the kernel sources hash to the value
-# they had when the counters were taken.
+# they had when the counters were taken (or to a later version whose step
+# kernel assembles to the same instructions: the source-term function made a
+# real call changed only the source-term instantiations).
 STEP_TRAFFIC_BYTES_PER_NODE = (1190166094.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "cb0c3833c4f59014d1f8685784ceb695f8b95d74502abdb0c21ddd4f5caef378"
+STEP_SOURCES_SHA256 = "c4732ffcd8b420bc10b0f23c91de06d83b36d205370c7050e0a8cc3069b71b7f"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

@@ -20,7 +20,11 @@
 
 namespace sgn {
 
-__device__ __forceinline__ void mms_source(double x, double y, double t, double g, double S[5]) {
+// A real call, not inlined: inlined at every evaluation of a step tile, the five
+// double-precision sincos evaluations took those kernels to 256 VGPRs plus
+// 58-174 AGPRs at one wave per SIMD; called, they use 143-254 VGPRs, no AGPRs,
+// a 48-byte call frame and two or three waves per SIMD.
+__device__ inline __attribute__((noinline)) void mms_source(double x, double y, double t, double g, double S[5]) {
   const double k = 6.283185307179586476925286766559;
   const double k2 = k * k;
   double sx, cx, sy, cy, s2x, c2x, s2y, c2y, st, ct;
