@@ -60,6 +60,10 @@ PATHS = {"pairs": (37, 2), "stages": (84, 4), "fused": (11, 1)}
 # reciprocal counts 1, a fused multiply-add 2.
 FLOPS_PER_NODE_STEP = 4 * 178 + 70
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# Untimed steps before the variants' timed runs (on a copy of the state): after an
+# idle spell of a few tens of ms the GPU runs the next ~30 launches up to 30%
+# slower while its clocks settle.
+SETTLE_STEPS = 64
 # HBM traffic of the step kernel on the default workload (4096^2 periodic FP64,
 # 32 x 16 tiles), from the FETCH_SIZE and WRITE_SIZE passes summarized in
 # profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
@@ -100,12 +104,15 @@ def lake_at_rest_energy(grid, b, mass):
     return 0.5 * grid.g * (M * (H * H - b * b)).sum()
 
 
-def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, repeats=1, drift_steps=0):
+def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, repeats=1, drift_steps=0, settle=0):
     """Times `repeats` runs of `steps` RK4 steps (after `warmup` untimed ones) with
     HIP events on the solver's stream; every graph a timed call replays is
     instantiated before the first event.  With drift_steps > 0, also records
     mass and energy over the first drift_steps steps from the initial state
-    (step kernel epilogue) for the comparison with the oracle."""
+    (step kernel epilogue) for the comparison with the oracle.  With settle > 0
+    (the variants, not the headline run), `settle` more untimed steps run on a
+    copy of the state just before the first timed run, so that the clocks have
+    left the idle spell behind; the state's own trajectory is unchanged."""
     import numpy as np
     import torch
     from paper_2601_02540_amd.binding import Solver
@@ -132,6 +139,10 @@ def run_gpu(problem, dtype, steps, warmup, label, path="pairs", tile_y=None, rep
     s.prepare_step(q, dt, steps)
     if warmup > 0:
         s.step(q, dt, warmup)
+    if settle > 0:
+        qs = q.clone()
+        s.profile_stages(qs, dt, settle)
+        del qs
     torch.cuda.synchronize()
     stream = s.stream
     secs = []
@@ -831,25 +842,26 @@ def main():
     if unknown:
         raise SystemExit(f"unknown variants: {sorted(unknown)}; choose from {sorted(ALL_VARIANTS)}")
     if "f32" in chosen:
-        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T, R, DS)
+        variants["periodic_f32"] = run_gpu(prob, torch.float32, args.steps, args.warmup, "periodic f32", P, T, R, DS,
+                                           SETTLE_STEPS)
         variants["periodic_f32"]["energy_diff_vs_f64_rel"] = (
             (variants["periodic_f32"]["energy_final"] - main_res["energy_final"]) / abs(main_res["energy_final"]))
     if "reflecting" in chosen:
         probr = W.random_phase_large(n, W.REFLECTING, seed=3)
         variants["reflecting_f64"] = run_gpu(probr, torch.float64, args.steps, args.warmup, "reflecting f64", P, T,
-                                             R, DS)
+                                             R, DS, SETTLE_STEPS)
         variants["reflecting_f32"] = run_gpu(probr, torch.float32, args.steps, args.warmup, "reflecting f32", P, T,
-                                             R, DS)
+                                             R, DS, SETTLE_STEPS)
     if "ensemble" in chosen:
         variants["ensemble_256_f32"] = run_ensemble(256, args.ensemble_steps, 4, torch.float32, "ensemble f32",
                                                     "pairs" if P == "pairs" else "fused")
     if "small" in chosen:
         small = W.gaussian_bump_periodic(64, seed=1)
         variants["gaussian_bump_64_f64"] = run_gpu(small, torch.float64, 200, 8, "gaussian bump 64 f64", P, T, R,
-                                                   200 if DS > 0 else 0)
+                                                   200 if DS > 0 else 0, SETTLE_STEPS)
         sol = W.soliton_over_bathymetry(512, seed=2)
         variants["soliton_512_reflecting_f64"] = run_gpu(sol, torch.float64, 500, 8, "soliton 512 f64", P, T, R,
-                                                         50 if DS > 0 else 0)
+                                                         50 if DS > 0 else 0, SETTLE_STEPS)
     if "adjoint" in chosen:
         variants["adjoint_gauges_1024_f64"] = run_adjoint(1024, args.adjoint_steps, "adjoint 1024 f64")
     if "relaxation" in chosen:
@@ -868,7 +880,7 @@ def main():
         for other in sorted(PATHS):
             if other != P:
                 variants[f"periodic_f64_{other}"] = run_gpu(prob, torch.float64, args.steps, args.warmup,
-                                                            f"periodic f64 {other}", other, T, R)
+                                                            f"periodic f64 {other}", other, T, R, 0, SETTLE_STEPS)
 
     cpu = None
     if not args.no_cpu_baseline or DS > 0:
