@@ -75,7 +75,7 @@ SETTLE_STEPS = 64
 STEP_TRAFFIC_BYTES_PER_NODE = (1190166094.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "c4732ffcd8b420bc10b0f23c91de06d83b36d205370c7050e0a8cc3069b71b7f"
+STEP_SOURCES_SHA256 = "2abd4d87e30e9a46065277f6e3f5e819be2240b0d2503b0ac6ba56b1067125c2"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

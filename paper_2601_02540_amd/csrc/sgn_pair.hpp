@@ -29,8 +29,9 @@ struct PairSmem {
 template <int BC>
 __device__ __forceinline__ int wrap_or_clamp(int g, int n) {
   if (BC == BC_PERIODIC) {
-    // g lies in [-2, n + 65]: one addition or a few subtractions wrap it
-    // (more than one only on axes shorter than the tile).
+    // g lies in [-4, n + 66] (a tile origin below n, the tile's extent and a
+    // halo of at most four nodes) and n >= 4: one addition or a few
+    // subtractions wrap it (more than one only on axes shorter than the tile).
     if (g < 0) g += n;
     while (g >= n) g -= n;
   } else {

@@ -65,6 +65,33 @@ def test_step_vjp_matches_oracle(bcs, ty, path):
     assert rel(host(bb) - bb0, bb_ref) <= 1e-11
 
 
+@pytest.mark.parametrize("shape", [(4, 4), (5, 7), (33, 17)])
+@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (REF, PER), (PER, REF)])
+def test_two_stage_reverse_on_grids_smaller_than_a_tile(shape, bcs, ty):
+    """The two-stage reverse kernels where one tile covers the grid (its ring
+    and its nodes past the edge are periodic images or wall copies) or spills
+    over it by one node, against the oracle's RK4 VJP."""
+    nx, ny = shape
+    g = W.Grid(nx, ny, -1.0, 2.0, 0.5, 2.0, bcs[0], bcs[1], 9.81, 500.0)
+    q, b = W.random_state(g, 5 * nx + ny, b_scale=0.05)
+    q[1:4] *= 0.1
+    rng = np.random.default_rng(nx * ny)
+    a = rng.standard_normal(q.shape)
+    bb0 = rng.standard_normal(b.shape)
+    dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
+    qb_ref, bb_ref = oracle.rk4_vjp(g, q, b, dt, a)
+    s = solver(g)
+    s.set_tile_y(ty)
+    s.set_step_path("fused")
+    s.set_bathymetry(dev(b))
+    qb = dev(a)
+    bb = dev(bb0)
+    s.step_vjp(dev(q), dt, qb, bb)
+    assert np.all(field_rel_err(host(qb), qb_ref) <= F64_TOL), (shape, bcs, ty)
+    assert rel(host(bb) - bb0, bb_ref) <= 1e-11
+
+
 def small_gauge_case(bc=REF, nx=48, ny=20, nsteps=24):
     gp = W.gauge_problem(nx=nx, ny=ny, gauges=6, radius=3.0)
     g = W.Grid(nx, ny, 0.0, 30.0, 0.0, 10.0, bc, bc, 9.81, 500.0)

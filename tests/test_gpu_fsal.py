@@ -150,6 +150,26 @@ def test_fixed_steps_match_oracle(bcs, ty, path):
     assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL)
 
 
+@pytest.mark.parametrize("shape", [(4, 4), (5, 7), (33, 17)])
+@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
+def test_fused_attempt_on_grids_smaller_than_a_tile(shape, bcs, ty):
+    """The attempt kernel where one tile covers the grid (rings and nodes past
+    the edge are periodic images or wall copies) or spills over it by one node:
+    3 fixed steps against the oracle."""
+    nx, ny = shape
+    g = W.Grid(nx, ny, -1.0, 2.0, 0.5, 2.0, bcs[0], bcs[1], 9.81, 500.0)
+    q, b = W.random_state(g, 3 * nx + ny, b_scale=0.05)
+    q[1:4] *= 0.1
+    q0 = oracle.init_aux(g, q, b)
+    dt = 0.3 * oracle.cfl_dt(g, q0, 0.5)
+    ref, _, na, _, rec_ref = oracle.fsal35(g, q0, b, 0.0, 3 * dt, dt, adaptive=False)
+    res, rec, got = run_gpu(g, q0, b, 3 * dt, dt, ty=ty, path="fused", adaptive=False)
+    assert res["accepted"] == na == 3 and res["rejected"] == 0
+    compare_records(rec, rec_ref)
+    assert np.all(field_rel_err(got, ref, STATE_FLOORS) <= F64_TOL), (shape, bcs, ty)
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_fp32_bounded_by_oracle_fp32_error(path):
     """FP32 storage and arithmetic, fixed steps: within the FP32 bound of the
