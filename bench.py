@@ -64,6 +64,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # idle spell of a few tens of ms the GPU runs the next ~30 launches up to 30%
 # slower while its clocks settle.
 SETTLE_STEPS = 64
+# Device memory the adjoint variant may fill with the stage states of the rollout's last
+# steps (beside its run that recomputes every step).
+ADJOINT_STORE_CAP_BYTES = 192 * 2**30
 # HBM traffic of the step kernel on the default workload (4096^2 periodic FP64,
 # 32 x 16 tiles), from the FETCH_SIZE and WRITE_SIZE passes summarized in
 # profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
@@ -309,6 +312,22 @@ def run_adjoint(n, steps, label):
     w = min(20, steps)
     s.gauge_loss_grad(z0, w, dt, nodes, target[:w].contiguous())  # warm-up of the adjoint buffers
     t_grad, (L, gz, gb) = timed(lambda: s.gauge_loss_grad(z0, steps, dt, nodes, target))
+    # the same gradient keeping the stage states of the rollout's last steps in free device memory
+    # (at most ADJOINT_STORE_CAP_BYTES), so that the reverse sweep recomputes only the others
+    state_bytes = 5 * g.nx * g.ny * 8
+    free_bytes, _ = torch.cuda.mem_get_info()
+    store = int(min(ADJOINT_STORE_CAP_BYTES, 0.6 * free_bytes))
+    kept = min(steps, max(0, (store // state_bytes - 1) // 4)) if store >= 5 * state_bytes else 0
+    kept_res = {"store_bytes": store, "kept_steps": kept}
+    if kept > 0:
+        s.set_adjoint_store(store)
+        s.gauge_loss_grad(z0, steps, dt, nodes, target)  # allocates the storage
+        t_kept, (L2, gz2, gb2) = timed(lambda: s.gauge_loss_grad(z0, steps, dt, nodes, target))
+        kept_res.update({"gradient_s": t_kept, "adjoint_to_forward": t_kept / t_fwd,
+                         "same_bits": bool(L2 == L and torch.equal(gz2, gz) and torch.equal(gb2, gb))})
+        s.set_adjoint_store(0)
+        log(f"[{label}] keeping the stage states of the last {kept} of {steps} steps ({store / 2**30:.0f} GiB): "
+            f"gradient {t_kept:.3f} s, adjoint:forward = {t_kept / t_fwd:.2f}, same bits {kept_res['same_bits']}")
     # context: the same forward on the four-stage path (84 values per node and step)
     s.set_step_path("stages")
     qs = q.clone()
@@ -321,6 +340,7 @@ def run_adjoint(n, steps, label):
            "forward_s": t_fwd, "forward_with_gauges_s": t_series, "gradient_s": t_grad,
            "adjoint_to_forward": t_grad / t_fwd,
            "forward_four_stage_s": t_fwd4, "adjoint_to_four_stage_forward": t_grad / t_fwd4,
+           "kept_rollout_tail": kept_res,
            "grad_norms": {"zeta0": float(torch.linalg.norm(gz)), "b": float(torch.linalg.norm(gb))}}
     log(f"[{label}] forward {t_fwd:.3f} s, gradient {t_grad:.3f} s, adjoint:forward = {t_grad / t_fwd:.2f} "
         f"(four-stage forward {t_fwd4:.3f} s: {t_grad / t_fwd4:.2f})")

@@ -101,8 +101,12 @@ typedef struct sgn_ctx sgn_ctx;
  * SGN_OPT_TILE_Y: 8 or 16.  Tile height of the stage and pair kernels (64 wide;
  *   default 8 for SGN_F64, 16 for SGN_F32) and shape of the step kernel's
  *   512-node tile (8 selects 64 x 8, 16 selects 32 x 16; default 16).  Setting
- *   the option sets both. */
-typedef enum { SGN_OPT_STEP_PATH = 0, SGN_OPT_TILE_Y = 1 } sgn_option;
+ *   the option sets both.
+ * SGN_OPT_ADJOINT_STORE: bytes of device memory (>= 0; default 0) that
+ *   sgn_gauge_loss_grad may fill with the states and stage states of the last
+ *   steps of its forward rollout, so that its reverse sweep need not recompute
+ *   them (see there). */
+typedef enum { SGN_OPT_STEP_PATH = 0, SGN_OPT_TILE_Y = 1, SGN_OPT_ADJOINT_STORE = 2 } sgn_option;
 typedef enum { SGN_PATH_PAIRS = 0, SGN_PATH_STAGES = 1, SGN_PATH_FUSED = 2 } sgn_step_path;
 
 /* Create a context on the current HIP device.  stream is a hipStream_t (NULL
@@ -315,8 +319,15 @@ sgn_status sgn_gauge_series(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, dou
  * runs the step VJPs backwards.  The forward steps follow the context's step
  * path (pair kernels on SGN_PATH_PAIRS, the step kernel otherwise), and so do
  * the step VJPs (as in sgn_step_vjp).  Memory: checkpoints plus 4*K+1 states
- * for a segment of K steps, plus five states of cotangent work buffers.  *loss is a host
- * double.  Synchronizes. */
+ * for a segment of K steps, plus five states of cotangent work buffers.  With
+ * SGN_OPT_ADJOINT_STORE = B bytes the forward rollout itself keeps the states
+ * and stage states of its last F = min(nsteps, (B / S - 1) / 4) steps (S the
+ * bytes of one state; 4*F+1 states, the same storage the segments reuse
+ * afterwards), the reverse sweep reverses those without recomputing them, and
+ * the checkpoints and segments cover the first nsteps - F steps only
+ * (checkpoint_every 0: ceil(sqrt(nsteps - F))).  Loss and gradients are the
+ * same bit for bit whatever B.  *loss is a host double.  Synchronizes.
+ * Errors: SGN_E_ALLOC when the storage cannot be allocated. */
 sgn_status sgn_gauge_loss_grad(sgn_ctx* ctx, const void* zeta0, int64_t nsteps, double dt, const int64_t* gauge_idx,
                                int32_t ngauges, const double* target, int64_t checkpoint_every, double* loss,
                                void* grad_zeta0, void* grad_b);

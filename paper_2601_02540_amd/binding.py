@@ -20,7 +20,7 @@ HEADER_PATH = os.path.join(ROOT, "include", "sgn.h")
 
 SGN_F64, SGN_F32 = 0, 1
 SGN_SRC_NONE, SGN_SRC_MMS = 0, 1
-SGN_OPT_STEP_PATH, SGN_OPT_TILE_Y = 0, 1
+SGN_OPT_STEP_PATH, SGN_OPT_TILE_Y, SGN_OPT_ADJOINT_STORE = 0, 1, 2
 SGN_PATH_PAIRS, SGN_PATH_STAGES, SGN_PATH_FUSED = 0, 1, 2
 
 
@@ -236,6 +236,11 @@ class Solver:
 
     def set_tile_y(self, ty: int):
         self.set_option(SGN_OPT_TILE_Y, ty)
+
+    def set_adjoint_store(self, nbytes: int):
+        """Device memory the gauge-loss gradient may fill with the states and stage
+        states of the rollout's last steps instead of recomputing them."""
+        self.set_option(SGN_OPT_ADJOINT_STORE, nbytes)
 
     def set_bathymetry(self, b):
         self._chk(self.lib.sgn_set_bathymetry(self.ctx, self._plane(b)))

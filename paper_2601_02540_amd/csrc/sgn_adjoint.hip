@@ -407,12 +407,23 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, do
   sgn_status st = gauge_args(c, zeta0, nsteps, dt, gauge_idx, ngauges);
   if (st) return st;
   if (!target || !loss || !grad_zeta0 || !grad_b) return fail(c, SGN_E_ARG, "NULL argument");
-  int64_t K = checkpoint_every > 0 ? checkpoint_every : (int64_t)std::ceil(std::sqrt((double)nsteps));
-  K = std::max<int64_t>(1, std::min<int64_t>(K, nsteps));
-  const int64_t nseg = (nsteps + K - 1) / K;
-  auto& a = c->adj;
-  if ((st = ensure_vjp_buffers(c)) || (st = ensure_stage_slots(c, (size_t)(4 * K + 1)))) return st;
   const size_t sb = state_bytes(c);
+  // The last F steps keep their states and stage states from the forward
+  // rollout (4F+1 states within the SGN_OPT_ADJOINT_STORE budget); the first
+  // T0 = nsteps - F are checkpointed every K steps and recomputed segment by
+  // segment in the reverse sweep.
+  const int64_t budget_states = c->adj_store_bytes / (int64_t)sb;
+  const int64_t F = budget_states >= 5 ? std::min<int64_t>(nsteps, (budget_states - 1) / 4) : 0;
+  const int64_t T0 = nsteps - F;
+  int64_t K = 1, nseg = 0;
+  if (T0 > 0) {
+    K = checkpoint_every > 0 ? checkpoint_every : (int64_t)std::ceil(std::sqrt((double)T0));
+    K = std::max<int64_t>(1, std::min<int64_t>(K, T0));
+    nseg = (T0 + K - 1) / K;
+  }
+  const size_t slots = (size_t)std::max<int64_t>(T0 > 0 ? 4 * K + 1 : 0, F > 0 ? 4 * F + 1 : 0);
+  auto& a = c->adj;
+  if ((st = ensure_vjp_buffers(c)) || (st = ensure_stage_slots(c, slots))) return st;
   bool ok = true;
   if (!a.state) ok = ok && hipMalloc(&a.state, sb) == hipSuccess;
   if (!a.qbar) ok = ok && hipMalloc(&a.qbar, sb) == hipSuccess;
@@ -437,43 +448,59 @@ sgn_status sgn_gauge_loss_grad(sgn_ctx* c, const void* zeta0, int64_t nsteps, do
     return fail(c, SGN_E_ALLOC, "adjoint rollout storage");
   }
   hipStream_t s = c->stream;
-  // 1. forward rollout: checkpoints every K steps, misfits, loss
+  // 1. forward rollout: checkpoints every K steps over the first T0 steps, then
+  //    the last F steps keeping every state and stage state (slot layout of a
+  //    segment: states 0..F at slots [0, F], stage triples from slot F+1);
+  //    misfits and loss throughout
   HIPCHK(c, hipMemsetAsync(a.loss, 0, sizeof(double), s));
   HIPCHK(c, launch_surface(c, zeta0, a.state));
   void* cur = a.state;
   void* oth = c->acc;
   for (int64_t n = 0; n < nsteps; ++n) {
-    if (n % K == 0) HIPCHK(c, hipMemcpyAsync(slot(a.ckpt, (size_t)(n / K), c), cur, sb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, rollout_step(c, s, cur, oth, dt));
-    std::swap(cur, oth);
+    if (n < T0) {
+      if (n % K == 0) HIPCHK(c, hipMemcpyAsync(slot(a.ckpt, (size_t)(n / K), c), cur, sb, hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, rollout_step(c, s, cur, oth, dt));
+      std::swap(cur, oth);
+    } else {
+      const int64_t k = n - T0;
+      if (k == 0) HIPCHK(c, hipMemcpyAsync(slot(a.stages, 0, c), cur, sb, hipMemcpyDeviceToDevice, s));
+      HIPCHK(c, forward_step_keep(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(F + 1 + 3 * k), c),
+                                  slot(a.stages, (size_t)(k + 1), c), dt));
+      cur = slot(a.stages, (size_t)(k + 1), c);
+    }
     HIPCHK(c, launch_record(c, cur, gauge_idx, ngauges, nullptr, target + n * ngauges, a.misfit + n * ngauges, a.loss));
   }
-  // 2. reverse sweep, one segment at a time: recompute the segment keeping every
-  //    state and stage state, then reverse its steps
+  // 2. reverse sweep: the kept steps, then one segment at a time (recompute
+  //    the segment keeping every state and stage state, then reverse its steps)
   HIPCHK(c, hipMemsetAsync(a.qbar, 0, sb, s));
   HIPCHK(c, hipMemsetAsync(grad_b, 0, c->N * c->esize, s));
+  // reverse of step n = n0 + k from the segment storage of length len
+  const auto reverse_from_slots = [&](int64_t n0, int64_t len, int64_t k) -> sgn_status {
+    const int64_t n = n0 + k;  // step n maps q_n to q_{n+1}; misfit row n belongs to q_{n+1}
+    if (c->p.dtype == SGN_F64)
+      hipLaunchKernelGGL(gauge_seed<double>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS),
+                         0, s, gauge_idx, ngauges, c->N, a.misfit + n * ngauges, (double*)a.qbar, (double*)grad_b);
+    else
+      hipLaunchKernelGGL(gauge_seed<float>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS),
+                         0, s, gauge_idx, ngauges, c->N, a.misfit + n * ngauges, (float*)a.qbar, (float*)grad_b);
+    HIPCHK(c, hipGetLastError());
+    void* out = nullptr;
+    HIPCHK(c, reverse_step(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c), a.qbar,
+                           grad_b, dt, &out));
+    if (out != a.qbar) std::swap(a.qbar, a.kb_b);  // both buffers belong to the context
+    return SGN_OK;
+  };
+  for (int64_t k = F - 1; k >= 0; --k)
+    if ((st = reverse_from_slots(T0, F, k))) return st;
   for (int64_t seg = nseg - 1; seg >= 0; --seg) {
     const int64_t n0 = seg * K;
-    const int64_t len = std::min<int64_t>(K, nsteps - n0);
-    // slot layout: states 0..len at slots [0, len], stage triples from slot len+1
+    const int64_t len = std::min<int64_t>(K, T0 - n0);
     HIPCHK(c, hipMemcpyAsync(slot(a.stages, 0, c), slot(a.ckpt, (size_t)seg, c), sb, hipMemcpyDeviceToDevice, s));
     for (int64_t k = 0; k < len; ++k)
       HIPCHK(c, forward_step_keep(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),
                                   slot(a.stages, (size_t)(k + 1), c), dt));
-    for (int64_t k = len - 1; k >= 0; --k) {
-      const int64_t n = n0 + k;  // step n maps q_n to q_{n+1}; misfit row n belongs to q_{n+1}
-      if (c->p.dtype == SGN_F64)
-        hipLaunchKernelGGL(gauge_seed<double>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS), 0, s, gauge_idx, ngauges, c->N,
-                           a.misfit + n * ngauges, (double*)a.qbar, (double*)grad_b);
-      else
-        hipLaunchKernelGGL(gauge_seed<float>, dim3((ngauges + GAUGE_THREADS - 1) / GAUGE_THREADS), dim3(GAUGE_THREADS), 0, s, gauge_idx, ngauges, c->N,
-                           a.misfit + n * ngauges, (float*)a.qbar, (float*)grad_b);
-      HIPCHK(c, hipGetLastError());
-      void* out = nullptr;
-      HIPCHK(c, reverse_step(c, s, slot(a.stages, (size_t)k, c), slot(a.stages, (size_t)(len + 1 + 3 * k), c),
-                             a.qbar, grad_b, dt, &out));
-      if (out != a.qbar) std::swap(a.qbar, a.kb_b);  // both buffers belong to the context
-    }
+    for (int64_t k = len - 1; k >= 0; --k)
+      if ((st = reverse_from_slots(n0, len, k))) return st;
   }
   // 3. reverse of the initialization
   const dim3 grid((unsigned)((c->N + 255) / 256)), block(256);

@@ -80,6 +80,7 @@ struct sgn_ctx {
   sgn_host::GraphCache totals_graph;  // steps with recorded totals (sgn_step_totals)
   double* totals_series = nullptr;    // the series pointer captured in totals_graph
   sgn_host::AdjointBuffers adj;
+  int64_t adj_store_bytes = 0;  // SGN_OPT_ADJOINT_STORE
   sgn_host::FsalBuffers fs;
   // Set only inside sgn_profile_stages: the step kernel is then launched with
   // these events bound to its own start and end.

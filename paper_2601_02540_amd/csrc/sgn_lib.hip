@@ -630,6 +630,9 @@ sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
     if (value != 8 && value != 16) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
     c->tile_y = (int)value;
     c->step_tile = (int)value;
+  } else if (option == SGN_OPT_ADJOINT_STORE) {
+    if (value < 0) return fail(c, SGN_E_ARG, "adjoint storage must be >= 0 bytes");
+    c->adj_store_bytes = value;
   } else {
     return fail(c, SGN_E_ARG, "unknown option");
   }
