@@ -66,7 +66,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 SETTLE_STEPS = 64
 # Device memory the adjoint variant may fill with the stage states of the rollout's last
 # steps (beside its run that recomputes every step).
-ADJOINT_STORE_CAP_BYTES = 192 * 2**30
+ADJOINT_STORE_CAP_BYTES = 240 * 2**30
 # HBM traffic of the step kernel on the default workload (4096^2 periodic FP64,
 # 32 x 16 tiles), from the FETCH_SIZE and WRITE_SIZE passes summarized in
 # profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
@@ -316,7 +316,7 @@ def run_adjoint(n, steps, label):
     # (at most ADJOINT_STORE_CAP_BYTES), so that the reverse sweep recomputes only the others
     state_bytes = 5 * g.nx * g.ny * 8
     free_bytes, _ = torch.cuda.mem_get_info()
-    store = int(min(ADJOINT_STORE_CAP_BYTES, 0.6 * free_bytes))
+    store = int(min(ADJOINT_STORE_CAP_BYTES, 0.8 * free_bytes))
     kept = min(steps, max(0, (store // state_bytes - 1) // 4)) if store >= 5 * state_bytes else 0
     kept_res = {"store_bytes": store, "kept_steps": kept}
     if kept > 0:
