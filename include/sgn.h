@@ -98,10 +98,14 @@ typedef struct sgn_ctx sgn_ctx;
  *   On the fused and pair paths the state alternates between the caller's
  *   buffer and a context buffer, so steps go in twos; an odd final step runs on
  *   the four-stage path.
- * SGN_OPT_TILE_Y: 8 or 16.  Tile height of the stage and pair kernels (64 wide;
- *   default 8 for SGN_F64, 16 for SGN_F32) and shape of the step kernel's
- *   512-node tile (8 selects 64 x 8, 16 selects 32 x 16; default 16).  Setting
- *   the option sets both.
+ * SGN_OPT_TILE_Y: 8, 16 or 24.  Tile height of the stage and pair kernels (64
+ *   wide; default 8 for SGN_F64, 16 for SGN_F32) and of the step kernel's tile
+ *   (8 selects 64 x 8, 16 selects 32 x 16, 24 selects 32 x 24: three owned
+ *   nodes per thread and the fewest redundant ring evaluations; default 24).
+ *   8 and 16 set both; 24 sets the step tile and height 16 for the stage and
+ *   pair kernels.  With a 32 x 24 step tile, steps that save stage states or
+ *   add source terms, and the adaptive pair's attempt kernel, run 32 x 16
+ *   tiles.  Every tile shape forms the same values.
  * SGN_OPT_ADJOINT_STORE: bytes of device memory (>= 0; default 0) that
  *   sgn_gauge_loss_grad may fill with the states and stage states of the last
  *   steps of its forward rollout, so that its reverse sweep need not recompute
@@ -369,14 +373,17 @@ sgn_status sgn_batch_mass_energy(sgn_batch* batch, double* mass, double* energy)
 /* Per-instance CFL steps (rule of sgn_cfl_dt) into a host array of n doubles.  Synchronizes. */
 sgn_status sgn_batch_cfl_dt(sgn_batch* batch, double cfl, double* dt);
 /* SGN_PATH_FUSED (default) or SGN_PATH_PAIRS (SGN_E_UNSUPPORTED otherwise).
- * Resets the tile height to the path's default (16; pairs in SGN_F64: 8). */
+ * Resets the tile height to the path's default (fused: 24; pairs: 8 in SGN_F64,
+ * 16 in SGN_F32). */
 sgn_status sgn_batch_set_step_path(sgn_batch* batch, int32_t path);
-/* Tile height (8 or 16; on the fused path 8 selects 64 x 8 tiles and 16
- * selects 32 x 16) and persistent workgroups per compute unit (1..16), or 0
- * for one workgroup per tile (the default: no persistent loop, fewer
- * registers). */
+/* Tile height (8 or 16, and 24 on the fused path; there 8 selects 64 x 8
+ * tiles, 16 selects 32 x 16 and 24 selects 32 x 24) and persistent
+ * workgroups per compute unit (1..16), or 0 for one workgroup per tile (the
+ * default: no persistent loop, fewer registers; the only choice for 32 x 24,
+ * SGN_E_UNSUPPORTED otherwise). */
 sgn_status sgn_batch_set_tiling(sgn_batch* batch, int32_t tile_y, int32_t blocks_per_cu);
-/* Time every (tile height 8 or 16, 0..6 workgroups per CU) candidate of the
+/* Time every (tile height 8, 16 or 24 (fused path, one workgroup per tile),
+ * 0..6 workgroups per CU) candidate of the
  * current step path on one step from the
  * registered states into scratch (the states are read, never written), keep
  * the fastest and report it (any output may be NULL; ms = time of one step).

@@ -52,7 +52,7 @@ template <typename T, int PAIR, int TX>
 hipError_t launch_vjp_pair_t(const sgn_ctx* c, hipStream_t s, const void* YA, const void* YB, const void* KinA,
                              const void* Qb, void* QbOut, void* Kout, void* Acc, void* Bb, double aA, double cqA,
                              double cyA, double cqB, double cyB) {
-  constexpr int TY = sgn::STEP_NODES / TX;
+  constexpr int TY = sgn::VjpGeom<TX>::TY;
   const int ntx = (c->p.nx + TX - 1) / TX;
   const int nty = (c->p.ny + TY - 1) / TY;
   const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
@@ -69,18 +69,18 @@ hipError_t launch_vjp_pair_t(const sgn_ctx* c, hipStream_t s, const void* YA, co
   return hipGetLastError();
 }
 
-// Two reverse stages in one launch (sgn::vjp_pair_kernel), on the step
-// kernel's tile shape.
+// Two reverse stages in one launch (sgn::vjp_pair_kernel), on 64 x 8 tiles
+// when the step kernel runs 64 x 8 tiles, on 32 x 16 tiles otherwise.
 template <int PAIR>
 hipError_t launch_vjp_pair(const sgn_ctx* c, hipStream_t s, const void* YA, const void* YB, const void* KinA,
                            const void* Qb, void* QbOut, void* Kout, void* Acc, void* Bb, double aA, double cqA,
                            double cyA, double cqB, double cyB) {
   if (c->p.dtype == SGN_F64) {
-    if (c->step_tile == 16)
+    if (c->step_tile != 8)
       return launch_vjp_pair_t<double, PAIR, 32>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
     return launch_vjp_pair_t<double, PAIR, 64>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
   }
-  if (c->step_tile == 16)
+  if (c->step_tile != 8)
     return launch_vjp_pair_t<float, PAIR, 32>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
   return launch_vjp_pair_t<float, PAIR, 64>(c, s, YA, YB, KinA, Qb, QbOut, Kout, Acc, Bb, aA, cqA, cyA, cqB, cyB);
 }

@@ -47,7 +47,7 @@ struct sgn_batch {
   bool q_set = false;
   bool desc_dirty = true;
   int path = SGN_PATH_FUSED;
-  int tile_y = 16;  // tile height; the step tile holds 512 nodes (8: 64 x 8, 16: 32 x 16), pair tiles are 64 wide
+  int tile_y = 24;  // tile height; step tiles 64 x 8, 32 x 16 or 32 x 24, pair tiles 64 x 8 or 64 x 16
   int blocks_per_cu = 0;  // one workgroup per tile
   int num_cus = 256;
   hipGraphExec_t gexec = nullptr;
@@ -84,7 +84,9 @@ void drop_graph(sgn_batch* b) {
 
 int work_key(const sgn_batch* b) { return b->path * 100 + b->tile_y; }
 
-int tile_width(const sgn_batch* b) { return b->path == SGN_PATH_FUSED ? sgn::STEP_NODES / b->tile_y : sgn::TILE_X; }
+int tile_width(const sgn_batch* b) {
+  return b->path == SGN_PATH_FUSED ? (b->tile_y == 8 ? sgn::StepGeom<8>::TX : sgn::StepGeom<16>::TX) : sgn::TILE_X;
+}
 
 // (Re)build the work list and descriptors for the current path and tile height.
 sgn_status build_work(sgn_batch* b) {
@@ -159,14 +161,15 @@ hipError_t launch_batch_pair(const sgn_batch* b, hipStream_t s, int pair, int pa
                          : launch_batch_pair_t<float, 8>(b, s, pair, parity, b->blocks_per_cu);
 }
 
-template <typename T, int TX>
+template <typename T, int TY>
 hipError_t launch_batch_step_t(const sgn_batch* b, hipStream_t s, int parity, int bpc) {
-  if (bpc == 0)
-    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX, false>), dim3(b->nwork), dim3(sgn::STAGE_THREADS), 0, s,
+  if (TY == 24 || bpc == 0) {  // one workgroup per 32 x 24 tile: no persistent instance of that shape
+    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TY, false>), dim3(b->nwork), dim3(sgn::STAGE_THREADS), 0, s,
                        b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
-  else
-    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TX, true>), dim3(persistent_grid(b, bpc)), dim3(sgn::STAGE_THREADS),
+  } else if constexpr (TY != 24) {
+    hipLaunchKernelGGL((sgn::batch_step_kernel<T, TY, true>), dim3(persistent_grid(b, bpc)), dim3(sgn::STAGE_THREADS),
                        0, s, b->d_desc, b->d_work, b->nwork, parity, b->d_flags);
+  }
   return hipGetLastError();
 }
 
@@ -174,10 +177,12 @@ hipError_t launch_batch_step_t(const sgn_batch* b, hipStream_t s, int parity, in
 hipError_t enqueue_batch_step(const sgn_batch* b, hipStream_t s, int parity) {
   if (b->path == SGN_PATH_FUSED) {
     if (b->dtype == SGN_F64)
-      return b->tile_y == 16 ? launch_batch_step_t<double, 32>(b, s, parity, b->blocks_per_cu)
-                             : launch_batch_step_t<double, 64>(b, s, parity, b->blocks_per_cu);
-    return b->tile_y == 16 ? launch_batch_step_t<float, 32>(b, s, parity, b->blocks_per_cu)
-                           : launch_batch_step_t<float, 64>(b, s, parity, b->blocks_per_cu);
+      return b->tile_y == 24   ? launch_batch_step_t<double, 24>(b, s, parity, b->blocks_per_cu)
+             : b->tile_y == 16 ? launch_batch_step_t<double, 16>(b, s, parity, b->blocks_per_cu)
+                               : launch_batch_step_t<double, 8>(b, s, parity, b->blocks_per_cu);
+    return b->tile_y == 24   ? launch_batch_step_t<float, 24>(b, s, parity, b->blocks_per_cu)
+           : b->tile_y == 16 ? launch_batch_step_t<float, 16>(b, s, parity, b->blocks_per_cu)
+                             : launch_batch_step_t<float, 8>(b, s, parity, b->blocks_per_cu);
   }
   hipError_t e = launch_batch_pair(b, s, 1, parity);
   if (e) return e;
@@ -228,7 +233,7 @@ sgn_status sgn_batch_create(int32_t n, const sgn_params* params, void* stream, s
   b->n = n;
   b->dtype = dtype;
   b->esize = dtype == SGN_F64 ? sizeof(double) : sizeof(float);
-  b->tile_y = 16;
+  b->tile_y = 24;
   b->stream = (hipStream_t)stream;
   for (int i = 0; i < n; ++i) {
     const sgn_params& p = params[i];
@@ -489,14 +494,17 @@ sgn_status sgn_batch_set_step_path(sgn_batch* b, int32_t path) {
   if (path != SGN_PATH_FUSED && path != SGN_PATH_PAIRS)
     return bfail(b, SGN_E_UNSUPPORTED, "a batch steps on the fused or the pair path");
   b->path = path;
-  b->tile_y = (path == SGN_PATH_PAIRS && b->dtype == SGN_F64) ? 8 : 16;  // measured best on MI355X
+  b->tile_y = path == SGN_PATH_PAIRS ? (b->dtype == SGN_F64 ? 8 : 16) : 24;  // measured best on MI355X
   drop_graph(b);
   return build_work(b);
 }
 
 sgn_status sgn_batch_set_tiling(sgn_batch* b, int32_t tile_y, int32_t blocks_per_cu) {
   if (!b) return SGN_E_ARG;
-  if (tile_y != 8 && tile_y != 16) return bfail(b, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
+  if (!(tile_y == 8 || tile_y == 16 || (tile_y == 24 && b->path == SGN_PATH_FUSED)))
+    return bfail(b, SGN_E_UNSUPPORTED, "tile height must be 8 or 16 (or 24 on the fused path)");
+  if (tile_y == 24 && blocks_per_cu != 0)
+    return bfail(b, SGN_E_UNSUPPORTED, "32 x 24 step tiles run one workgroup per tile (blocks_per_cu 0)");
   if (blocks_per_cu < 0 || blocks_per_cu > 16) return bfail(b, SGN_E_ARG, "blocks per CU must be in [0, 16]");
   b->tile_y = tile_y;
   b->blocks_per_cu = blocks_per_cu;
@@ -517,7 +525,7 @@ sgn_status sgn_batch_autotune(sgn_batch* b, const double* dt, int32_t* tile_y, i
   }
   // Candidates are timed on one step from q into the scratch buffer (parity 0),
   // which reads the states but never writes them.
-  const int tys[2] = {8, 16};
+  const int tys[3] = {8, 16, 24};
   const int bpcs[7] = {0, 1, 2, 3, 4, 5, 6};
   double best = 1e300;
   int best_ty = b->tile_y, best_bpc = b->blocks_per_cu;
@@ -525,9 +533,11 @@ sgn_status sgn_batch_autotune(sgn_batch* b, const double* dt, int32_t* tile_y, i
   BCHK(b, hipEventCreate(&e0));
   BCHK(b, hipEventCreate(&e1));
   for (int ty : tys) {
+    if (ty == 24 && b->path != SGN_PATH_FUSED) continue;
     b->tile_y = ty;
     if ((st = build_work(b)) || (st = push_desc(b))) break;
     for (int bpc : bpcs) {
+      if (ty == 24 && bpc != 0) continue;  // one workgroup per 32 x 24 tile
       b->blocks_per_cu = bpc;
       hipError_t e = enqueue_batch_step(b, b->stream, 0);  // warm-up
       if (!e) e = hipEventRecord(e0, b->stream);

@@ -90,12 +90,12 @@ __global__ __launch_bounds__(STAGE_THREADS) void batch_pair_kernel(const InstDes
   }
 }
 
-// Work item w of one RK4 step by the step tile (tiles of TX x 512/TX).
-template <typename T, int TX>
-__device__ __forceinline__ void batch_step_item(StepSmem<T, TX, 1>& s, const InstDesc* __restrict__ desc,
+// Work item w of one RK4 step by the step tile (tiles of TX x TY, StepGeom).
+template <typename T, int TY>
+__device__ __forceinline__ void batch_step_item(StepSmem<T, TY, 1>& s, const InstDesc* __restrict__ desc,
                                                 const int* __restrict__ work_inst, int w, int parity,
                                                 int* __restrict__ flags) {
-  constexpr int TY = StepGeom<TX>::TY;
+  constexpr int TX = StepGeom<TY>::TX;
   const int inst = work_inst[w];
   const InstDesc d = desc[inst];
   const int t = w - d.tile_base;
@@ -107,21 +107,21 @@ __device__ __forceinline__ void batch_step_item(StepSmem<T, TX, 1>& s, const Ins
   const double dt = d.dt;
   const T c6 = T(dt / 6.0), c3 = T(dt / 3.0), c2 = T(dt / 2.0), c1 = T(dt);
   switch (d.gc.bc_x * 2 + d.gc.bc_y) {
-    case 0: step_tile<T, 0, 0, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
-    case 1: step_tile<T, 0, 1, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
-    case 2: step_tile<T, 1, 0, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
-    default: step_tile<T, 1, 1, false, TX, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+    case 0: step_tile<T, 0, 0, false, TY, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+    case 1: step_tile<T, 0, 1, false, TY, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+    case 2: step_tile<T, 1, 0, false, TY, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
+    default: step_tile<T, 1, 1, false, TY, false>(s, d.gc, i0, j0, cur, b, oth, c6, c3, c2, c1, 0.0, dt, flags + inst, nullptr); break;
   }
 }
 
 // One RK4 step of every instance.  parity and PERSIST as for batch_pair_kernel.
-template <typename T, int TX, bool PERSIST>
+template <typename T, int TY, bool PERSIST>
 __global__ __launch_bounds__(STAGE_THREADS) void batch_step_kernel(const InstDesc* __restrict__ desc,
                                                                    const int* __restrict__ work_inst, int nwork,
                                                                    int parity, int* __restrict__ flags) {
-  __shared__ StepSmem<T, TX, 1> s;
+  __shared__ StepSmem<T, TY, 1> s;
   if (!PERSIST) {
-    batch_step_item<T, TX>(s, desc, work_inst, xcd_tile(blockIdx.x, nwork), parity, flags);
+    batch_step_item<T, TY>(s, desc, work_inst, xcd_tile(blockIdx.x, nwork), parity, flags);
     return;
   }
   const int xcd = blockIdx.x & 7;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void batch_step_kernel(const InstDes
   const int start = (int)((long long)nwork * xcd / 8);
   const int end = (int)((long long)nwork * (xcd + 1) / 8);
   for (int w = start + k; w < end; w += blocks_per_xcd) {
-    batch_step_item<T, TX>(s, desc, work_inst, w, parity, flags);
+    batch_step_item<T, TY>(s, desc, work_inst, w, parity, flags);
     __syncthreads();
   }
 }

@@ -79,14 +79,21 @@ hipError_t enqueue_attempt_ty(const sgn_ctx* c, hipStream_t s, void* q, double* 
     else hipLaunchKernelGGL((sgn::fsal_kernel<T, 1, 1, R, TY>), grid, block, 0, s, c->gc, a);                \
   } while (0)
   if (c->step_path == SGN_PATH_FUSED) {
-    // S2 .. S5 in one launch of the step tile
-    constexpr int TXA = 64, TXB = 32;
-    const int tx = c->step_tile == 16 ? TXB : TXA;
-    const int sx = (c->p.nx + tx - 1) / tx, sy = (c->p.ny + sgn::STEP_NODES / tx - 1) / (sgn::STEP_NODES / tx);
+    // S2 .. S5 in one launch of the step tile (32 x 16 where the context's step
+    // tile is 32 x 24: the attempt's 32 x 24 instances reach the register limit)
+    const int ty = c->step_tile == 8 ? 8 : 16;
+    const int tx = ty == 8 ? sgn::StepGeom<8>::TX : sgn::StepGeom<16>::TX;
+    const int sx = (c->p.nx + tx - 1) / tx, sy = (c->p.ny + ty - 1) / ty;
     const dim3 sgrid((unsigned)(sx * sy));
-#define SGN_FSTEP(TX)                                                                                            do {                                                                                                             if (bx == 0 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 0, TX>), sgrid, block, 0, s, c->gc, a);     else if (bx == 0 && by == 1) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 1, TX>), sgrid, block, 0, s, c->gc, a);     else if (bx == 1 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 0, TX>), sgrid, block, 0, s, c->gc, a);     else hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 1, TX>), sgrid, block, 0, s, c->gc, a);                  } while (0)
-    if (tx == TXB) SGN_FSTEP(TXB);
-    else SGN_FSTEP(TXA);
+#define SGN_FSTEP(TY_)                                                                                             \
+  do {                                                                                                             \
+    if (bx == 0 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 0, TY_>), sgrid, block, 0, s, c->gc, a);      \
+    else if (bx == 0 && by == 1) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 1, TY_>), sgrid, block, 0, s, c->gc, a); \
+    else if (bx == 1 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 0, TY_>), sgrid, block, 0, s, c->gc, a); \
+    else hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 1, TY_>), sgrid, block, 0, s, c->gc, a);                   \
+  } while (0)
+    if (ty == 16) SGN_FSTEP(16);
+    else SGN_FSTEP(8);
 #undef SGN_FSTEP
   } else {
     SGN_ROLE(sgn::FS_S2);

@@ -254,15 +254,15 @@ __global__ __launch_bounds__(STAGE_THREADS) void fsal_kernel(const GridConst gc,
 }
 
 // S2 .. S5 of one attempt in one launch (the default step path): the step
-// tile in its RK_FSAL mode over TX x (512 / TX) tiles with a four-node halo.
+// tile in its RK_FSAL mode over TX x TY tiles (StepGeom) with a four-node halo.
 // Reads y, k_1 and b, writes y_{n+1} and e'; the intermediate stages Y_2 .. Y_5
 // stay in LDS (the rings around each tile are evaluated redundantly).  21
 // values per node instead of the 99 of the four role kernels.  Same arithmetic
 // as the roles node by node, so the same bits.
-template <typename T, int BCX, int BCY, int TX>
+template <typename T, int BCX, int BCY, int TY>
 __global__ __launch_bounds__(STAGE_THREADS) void fsal_step_kernel(const GridConst gc, const FsalArgs<T> a) {
-  constexpr int TY = StepGeom<TX>::TY;
-  __shared__ StepSmem<T, TX, 1> s;
+  constexpr int TX = StepGeom<TY>::TX;
+  __shared__ StepSmem<T, TY, 1> s;
   const AdaptCtl* ctl = a.ctl;
   if (ctl->done) return;  // the same for the whole grid
   const int cur = ctl->cur;
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(STAGE_THREADS) void fsal_step_kernel(const GridCons
   const int ntx = (gc.nx + TX - 1) / TX;
   const int nty = (gc.ny + TY - 1) / TY;
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  step_tile<T, BCX, BCY, false, TX, false, 1, EPI_NONE, RK_FSAL>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY,
+  step_tile<T, BCX, BCY, false, TY, false, 1, EPI_NONE, RK_FSAL>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY,
                                                                  a.q[cur], a.b, a.q[cur ^ 1], T(0), T(0), T(0),
                                                                  T(0), 0.0, 0.0, nullptr, nullptr, nullptr, &fx);
 }

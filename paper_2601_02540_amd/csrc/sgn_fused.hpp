@@ -1,7 +1,8 @@
 // sgn_fused.hpp -- one classical RK4 step in one kernel.
 //
-// Each workgroup owns a tile of TX x TY = 512 nodes and stages the state q with
-// a four-node halo of (h, u, v, w, eta, b, 1/h) in LDS.  The four right-hand
+// Each workgroup owns a tile of TX x TY nodes (32 x 24 by default, or 32 x 16
+// or 64 x 8) and stages the state q with a four-node halo of
+// (h, u, v, w, eta, b, 1/h) in LDS.  The four right-hand
 // sides of the step are evaluated on shrinking regions, since each evaluation
 // reaches one node further than the stage it reads:
 //   k1 = f(q)   on the tile and the rings at distance 1..3,  Y2 = q + dt/2 k1
@@ -12,12 +13,13 @@
 // nodes.  Each intermediate stage overwrites the previous one in LDS (b is
 // kept).  Only q and b are read and q_new written: 11 values per node and
 // step from HBM, against 37 for the two pair kernels and 84 for four stage
-// kernels.  The price is the ring evaluations (48 wave evaluations per tile and
-// step for a 64 x 8 tile, 44 for 32 x 16, against 32 without rings).
+// kernels.  The price is the ring evaluations: 1.24 right-hand sides per owned
+// node and stage for a 32 x 24 tile, 1.31 for 32 x 16 and 1.42 for 64 x 8.
 //
-// Thread map: thread t owns the two tile nodes (t mod TX, 2 floor(t / TX) + k),
-// k = 0, 1, in every stage, so their q and acc stay in registers; the pair
-// shares two of its y-neighbours.  Ring nodes are numbered by distance (all of
+// Thread map: thread t owns the NO = TX TY / 256 tile nodes
+// (t mod TX, NO floor(t / TX) + k), k < NO (three for 32 x 24, two for the
+// others), in every stage, so their q and acc stay in registers; each node
+// shares y-neighbours with the one below it.  Ring nodes are numbered by distance (all of
 // ring 1 first, then ring 2, then ring 3); thread t evaluates ring nodes t and
 // t + 256 in every stage whose region contains them, so the q of a ring node is
 // read from LDS once, in the first stage.
@@ -32,12 +34,15 @@
 
 namespace sgn {
 
-constexpr int STEP_NODES = 512;  // owned nodes per tile (two per thread)
-constexpr int STEP_HALO = 4;     // one node per right-hand side of the step
+constexpr int STEP_HALO = 4;  // one node per right-hand side of the step
 
-template <int TX>
+// Tile shapes of the step kernel: TX x TY with TY = 24 (32 wide, three owned
+// nodes per thread), 16 (32 wide) or 8 (64 wide; both two per thread).
+template <int TY_>
 struct StepGeom {
-  static constexpr int TY = STEP_NODES / TX;
+  static constexpr int TY = TY_;
+  static constexpr int TX = TY == 8 ? 64 : 32;
+  static constexpr int NO = TX * TY / STAGE_THREADS;  // owned nodes per thread
   static constexpr int RX = TX + 2 * STEP_HALO;
   static constexpr int RY = TY + 2 * STEP_HALO;
   // nodes of the ring at distance d around the tile
@@ -45,8 +50,8 @@ struct StepGeom {
   static constexpr int RING1 = ring(1);
   static constexpr int RING2 = RING1 + ring(2);
   static constexpr int RING3 = RING2 + ring(3);
-  static_assert(STEP_NODES % TX == 0 && STAGE_THREADS % TX == 0, "tile width must divide 256");
-  static_assert(2 * STAGE_THREADS / TX == TY, "each thread owns two vertically adjacent nodes");
+  static_assert(TY == 8 || TY == 16 || TY == 24, "tile shapes 64 x 8, 32 x 16, 32 x 24");
+  static_assert(NO * STAGE_THREADS == TX * TY && (NO == 2 || NO == 3), "two or three owned nodes per thread");
   static_assert(RING3 <= 2 * STAGE_THREADS, "two ring slots per thread");
 };
 
@@ -56,9 +61,9 @@ struct StepGeom {
 // inline) keep unpadded rows (PAD = 0): their reflecting variant returned wrong
 // values near the x-walls with padded rows, a failure not explained by the
 // source; unpadded they agree bit for bit with the four-stage path.
-template <typename T, int TX, int PAD>
+template <typename T, int TY, int PAD>
 struct StepSmem {
-  T f[7][StepGeom<TX>::RY][StepGeom<TX>::RX + PAD];  // h u v w eta b 1/h, then the current stage (b kept)
+  T f[7][StepGeom<TY>::RY][StepGeom<TY>::RX + PAD];  // h u v w eta b 1/h, then the current stage (b kept)
 };
 
 // The node's values behind an empty asm statement: the compiler can no longer
@@ -95,9 +100,10 @@ struct FsalStage {
 };
 
 // Position (r, c), relative to the tile origin, of ring node m (0 <= m < RING3).
-template <int TX>
+template <int TY>
 __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
-  using G = StepGeom<TX>;
+  using G = StepGeom<TY>;
+  constexpr int TX = G::TX;
   int d;
   if (m < G::RING1) {
     d = 1;
@@ -136,16 +142,17 @@ __device__ __forceinline__ void ring_node(int m, int& r, int& c) {
 // y_n, qout receives y_{n+1}, *fx supplies k_1, the coefficients and the e'
 // output; c6 .. c1, t0, dt and flag are unused (the health of y_{n+1} is
 // checked by the attempt's FSAL evaluation).
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE, int PAD, int EPI = EPI_NONE,
+template <typename T, int BCX, int BCY, bool SRC, int TY, bool SAVE, int PAD, int EPI = EPI_NONE,
           int RK = RK_CLASSIC>
-__device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridConst& gc, int i0, int j0,
+__device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridConst& gc, int i0, int j0,
                                           const T* __restrict__ q, const T* __restrict__ bplane,
                                           T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
                                           int* __restrict__ flag, T* __restrict__ ysave,
                                           double* __restrict__ rpart = nullptr,
                                           const FsalStage<T>* __restrict__ fx = nullptr) {
   static_assert(RK == RK_CLASSIC || (!SRC && !SAVE && EPI == EPI_NONE), "the FSAL tile has no extras");
-  using G = StepGeom<TX>;
+  using G = StepGeom<TY>;
+  constexpr int TX = G::TX, NO = G::NO;
   constexpr int RX = G::RX;
   constexpr int REGION = G::RX * G::RY;
 
@@ -157,8 +164,8 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   //    Every load of the region is issued before the first one is waited
   //    for: the step kernel reads little per unit of work, so its bandwidth
   //    is set by how many bytes each workgroup keeps in flight.
-  constexpr int NF = RK == RK_FSAL ? 2 : 1;
-  T yown[NF][5], yring[NF][5];  // RK_FSAL: y of the owned and ring nodes
+  constexpr int NF = RK == RK_FSAL ? 1 : 0;
+  T yown[NF ? NO : 1][5], yring[NF ? 2 : 1][5];  // RK_FSAL: y of the owned and ring nodes
   {
     constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
     T v[ITER][6];
@@ -201,15 +208,18 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
       // LDS holds y: the owned and ring nodes take their y from it (the ring's
       // periodic images and clamped wall copies included), then Y_2 =
       // y + h c_2 k_1 and its 1/h replace it
-      const int lx_ = tid % TX, ly_ = 2 * (tid / TX);
+      const int lx_ = tid % TX, ly_ = NO * (tid / TX);
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < NO; ++k) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) yown[k][f] = s.f[f][ly_ + k + STEP_HALO][lx_ + STEP_HALO];
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
         const int m = tid + k * STAGE_THREADS;
         if (m < G::RING3) {
           int r_, c_;
-          ring_node<TX>(m, r_, c_);
+          ring_node<TY>(m, r_, c_);
 #pragma unroll
           for (int f = 0; f < 5; ++f) yring[k][f] = s.f[f][r_ + STEP_HALO][c_ + STEP_HALO];
         }
@@ -234,13 +244,13 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
   }
 
   __builtin_amdgcn_s_setprio(0);
-  // Owned nodes (lx, ly0 + k), k = 0, 1, and ring slots of this thread.
+  // Owned nodes (lx, ly0 + k), k < NO, and ring slots of this thread.
   const int lx = tid % TX;
-  const int ly0 = 2 * (tid / TX);
+  const int ly0 = NO * (tid / TX);
   const int i = i0 + lx;
-  bool own_dom[2];
+  bool own_dom[NO];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < NO; ++k) {
     const int j = j0 + ly0 + k;
     own_dom[k] = on_axis<BCX>(i, nx) && on_axis<BCY>(j, ny);
   }
@@ -253,23 +263,26 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     ring_c[k] = 0;
     ring_ok[k] = false;
     if (m < G::RING3) {
-      ring_node<TX>(m, ring_r[k], ring_c[k]);
+      ring_node<TY>(m, ring_r[k], ring_c[k]);
       ring_ok[k] = on_axis<BCX>(i0 + ring_c[k], nx) && on_axis<BCY>(j0 + ring_r[k], ny);
     }
   }
   __syncthreads();
 
-  T qo[2][5], acc[2][5], qr[2][5];
-  T k1o[NF][5];  // RK_FSAL: k_1 of the owned nodes
+  T qo[NO][5], acc[NO][5], qr[2][5];
+  T k1o[NF ? NO : 1][5];  // RK_FSAL: k_1 of the owned nodes
   if constexpr (RK == RK_FSAL) {
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-#pragma unroll
-      for (int f = 0; f < 5; ++f) qo[k][f] = yown[k][f];
       if (tid + k * STAGE_THREADS < G::RING3) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) qr[k][f] = yring[k][f];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k) {
+#pragma unroll
+      for (int f = 0; f < 5; ++f) qo[k][f] = yown[k][f];
       if (own_dom[k]) {
         const size_t ow = (size_t)wrap_or_clamp<BCY>(j0 + ly0 + k, ny) * nx + wrap_or_clamp<BCX>(i, nx);
 #pragma unroll
@@ -293,11 +306,12 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     }
     const double ts = t0 + (st == 1 ? 0.0 : (st == 4 ? dt : 0.5 * dt));
     const int ring_lim = st == 1 ? G::RING3 : (st == 2 ? G::RING2 : G::RING1);
-    T ro[2][5], rr[2][5];
-    // Owned nodes.  Node 1 lies just above node 0 in y, so whenever node 1 is
-    // in the domain (then j0 + ly0 + 1 is neither the first row nor beyond the
-    // last) its centre is node 0's upper y-neighbour and its lower
-    // y-neighbour is node 0's centre: the pair reads 8 nodes from LDS, not 10.
+    T ro[NO][5], rr[2][5];
+    // Owned nodes.  Node k lies just above node k - 1 in y, so whenever node k
+    // is in the domain (then j0 + ly0 + k - 1 is neither the first row nor
+    // beyond the last) its lower y-neighbour is node k - 1's centre, and node
+    // 1's centre is node 0's upper y-neighbour: the pair reads 8 nodes from
+    // LDS, not 10, and three nodes read 12, not 15.
     const auto finish = [&](int k, const Rates<T>& kk, const Node<T>& cn) {
       const int j = j0 + ly0 + k;
       const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
@@ -402,6 +416,22 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
           const Node<T> xp = lds_load<T>(s, r + 1, c + ax.op);
           const Node<T> up1 = lds_load<T>(s, r + 1 + ay1.op, c);
           finish(1, node_rates<T, BCX, BCY, SRC>(upn, xm, xp, c0n, up1, ax, ay1, i, j + 1, gc, ts), upn);
+          if constexpr (NO == 3) {
+            __builtin_amdgcn_sched_barrier(0);
+            const bool run2 = st < 4 ? own_dom[2] : (i < nx && j + 2 < ny);
+            if (run2) {
+              // node 1's centre re-enters as an opaque value; node 2's own
+              // centre is read again (taking it from node 1's upper neighbour
+              // changes how node 1's arithmetic is fused)
+              const Node<T> c1n = opaque_node(upn);
+              const AxisStencil<BCY> ay2(j + 2, ny, gc.inv2dy, gc.invdy);
+              const Node<T> c2 = lds_load<T>(s, r + 2, c);
+              const Node<T> xm2 = lds_load<T>(s, r + 2, c + ax.om);
+              const Node<T> xp2 = lds_load<T>(s, r + 2, c + ax.op);
+              const Node<T> up2 = lds_load<T>(s, r + 2 + ay2.op, c);
+              finish(2, node_rates<T, BCX, BCY, SRC>(c2, xm2, xp2, c1n, up2, ax, ay2, i, j + 2, gc, ts), c2);
+            }
+          }
         }
       }
     }
@@ -431,7 +461,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
     __syncthreads();
     // the stage just formed replaces the one read
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < NO; ++k) {
       if (!own_dom[k]) continue;
       const int r = ly0 + k + STEP_HALO, c = lx + STEP_HALO;
 #pragma unroll
@@ -464,18 +494,18 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TX, PAD>& s, const GridCon
 }
 
 // EPI != EPI_NONE: rpart holds 4 doubles per tile, in tile order.
-template <typename T, int BCX, int BCY, bool SRC, int TX, bool SAVE = false, int EPI = EPI_NONE>
+template <typename T, int BCX, int BCY, bool SRC, int TY, bool SAVE = false, int EPI = EPI_NONE>
 __global__ __launch_bounds__(STAGE_THREADS) void step_kernel(const GridConst gc, const T* __restrict__ q,
                                                              const T* __restrict__ bplane, T* __restrict__ qout,
                                                              T c6, T c3, T c2, T c1, double t0, double dt,
                                                              int* __restrict__ flag, T* __restrict__ ysave,
                                                              double* __restrict__ rpart) {
-  constexpr int TY = StepGeom<TX>::TY;
-  __shared__ StepSmem<T, TX, SRC ? 0 : 1> s;
+  constexpr int TX = StepGeom<TY>::TX;
+  __shared__ StepSmem<T, TY, SRC ? 0 : 1> s;
   const int ntx = (gc.nx + TX - 1) / TX;
   const int nty = (gc.ny + TY - 1) / TY;
   const int tile = xcd_tile(blockIdx.x, ntx * nty);
-  step_tile<T, BCX, BCY, SRC, TX, SAVE, SRC ? 0 : 1, EPI>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane,
+  step_tile<T, BCX, BCY, SRC, TY, SAVE, SRC ? 0 : 1, EPI>(s, gc, (tile % ntx) * TX, (tile / ntx) * TY, q, bplane,
                                                           qout, c6, c3, c2, c1, t0, dt, flag, ysave,
                                                           EPI != EPI_NONE ? rpart + 4 * tile : nullptr);
 }

@@ -157,10 +157,10 @@ hipError_t launch_pair(const sgn_ctx* c, hipStream_t s, const void* Yin, const v
   return launch_pair_ty<float, PAIR, 8>(c, s, Yin, qn, acc_io, yb, c1_acc, c1_y, c2_acc, c2_y, t1, t2);
 }
 
-template <typename T, int TX>
-hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
+template <typename T, int TY>
+hipError_t launch_fused_ty(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
                            void* ysave, double* rpart, int epi) {
-  constexpr int TY = sgn::STEP_NODES / TX;
+  constexpr int TX = sgn::StepGeom<TY>::TX;
   const int ntx = (c->p.nx + TX - 1) / TX;
   const int nty = (c->p.ny + TY - 1) / TY;
   const dim3 grid((unsigned)(ntx * nty)), block(sgn::STAGE_THREADS);
@@ -172,11 +172,11 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 #define SGN_LAUNCH_K(BX, BY, S, SV, RX)                                                                         \
   do {                                                                                                         \
     if (c->prof_start)                                                                                         \
-      hipExtLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->prof_start,    \
+      hipExtLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TY, SV, RX>), grid, block, 0, s, c->prof_start,    \
                             c->prof_stop, 0, c->gc, qp, bp, op, (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0),  \
                             (T)dt, t0, dt, c->flag, ys, rpart);                                               \
     else                                                                                                       \
-      hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TX, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,   \
+      hipLaunchKernelGGL((sgn::step_kernel<T, BX, BY, S, TY, SV, RX>), grid, block, 0, s, c->gc, qp, bp, op,   \
                          (T)(dt / 6.0), (T)(dt / 3.0), (T)(dt / 2.0), (T)dt, t0, dt, c->flag, ys, rpart);     \
   } while (0)
 #define SGN_LAUNCH(BX, BY, S) SGN_LAUNCH_K(BX, BY, S, false, sgn::EPI_NONE)
@@ -191,17 +191,19 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
     else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, false, sgn::EPI_TOTALS);
     else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, false, sgn::EPI_TOTALS);
     else SGN_LAUNCH_K(1, 1, false, false, sgn::EPI_TOTALS);
-  } else if (ys) {  // stage saving (no source terms)
-    if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true, sgn::EPI_NONE);
-    else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true, sgn::EPI_NONE);
-    else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true, sgn::EPI_NONE);
-    else SGN_LAUNCH_K(1, 1, false, true, sgn::EPI_NONE);
+  } else if (ys) {  // stage saving (no source terms; not on 32 x 24 tiles)
+    if constexpr (TY != 24) {
+      if (bx == 0 && by == 0) SGN_LAUNCH_K(0, 0, false, true, sgn::EPI_NONE);
+      else if (bx == 0 && by == 1) SGN_LAUNCH_K(0, 1, false, true, sgn::EPI_NONE);
+      else if (bx == 1 && by == 0) SGN_LAUNCH_K(1, 0, false, true, sgn::EPI_NONE);
+      else SGN_LAUNCH_K(1, 1, false, true, sgn::EPI_NONE);
+    }
   } else if (!src) {
     if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, false);
     else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, false);
     else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, false);
     else SGN_LAUNCH(1, 1, false);
-  } else {
+  } else if constexpr (TY != 24) {  // source terms (not on 32 x 24 tiles)
     if (bx == 0 && by == 0) SGN_LAUNCH(0, 0, true);
     else if (bx == 0 && by == 1) SGN_LAUNCH(0, 1, true);
     else if (bx == 1 && by == 0) SGN_LAUNCH(1, 0, true);
@@ -215,14 +217,20 @@ hipError_t launch_fused_tx(const sgn_ctx* c, hipStream_t s, const void* qin, voi
 // One RK4 step in one kernel, from state buffer `qin` into `qout` (distinct);
 // with `ysave`, also the stage states Y2, Y3, Y4 (three consecutive states);
 // with `rpart`, also the epilogue sums `epi` (sgn::EPI_*) of every tile.
+// Stage saving and source terms run on 32 x 16 tiles where the context's
+// step tile is 32 x 24 (their 32 x 24 instances reach the register limit);
+// every tile shape forms the same values.
 hipError_t launch_fused(const sgn_ctx* c, hipStream_t s, const void* qin, void* qout, double dt, double t0,
                         void* ysave = nullptr, double* rpart = nullptr, int epi = sgn::EPI_NONE) {
+  const int ty = c->step_tile == 24 && (ysave || c->p.source == SGN_SRC_MMS) ? 16 : c->step_tile;
   if (c->p.dtype == SGN_F64) {
-    if (c->step_tile == 16) return launch_fused_tx<double, 32>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
-    return launch_fused_tx<double, 64>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+    if (ty == 24) return launch_fused_ty<double, 24>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+    if (ty == 16) return launch_fused_ty<double, 16>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+    return launch_fused_ty<double, 8>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
   }
-  if (c->step_tile == 16) return launch_fused_tx<float, 32>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
-  return launch_fused_tx<float, 64>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+  if (ty == 24) return launch_fused_ty<float, 24>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+  if (ty == 16) return launch_fused_ty<float, 16>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
+  return launch_fused_ty<float, 8>(c, s, qin, qout, dt, t0, ysave, rpart, epi);
 }
 
 // Two RK4 steps on the fused path: q -> acc -> q.
@@ -358,13 +366,13 @@ hipError_t enqueue_step_into(const sgn_ctx* c, hipStream_t s, const void* cur, v
 }
 
 int step_tiles(const sgn_ctx* c) {
-  const int tx = c->step_tile == 16 ? 32 : 64;
-  const int ty = sgn::STEP_NODES / tx;
+  const int ty = c->step_tile;
+  const int tx = ty == 8 ? sgn::StepGeom<8>::TX : sgn::StepGeom<16>::TX;
   return ((c->p.nx + tx - 1) / tx) * ((c->p.ny + ty - 1) / ty);
 }
 
 sgn_status ensure_tile_partials(sgn_ctx* c) {
-  // room for the larger tile count of the two tile shapes
+  // room for the largest tile count of the tile shapes (32 x 24 has the fewest tiles)
   const size_t nx = (size_t)c->p.nx, ny = (size_t)c->p.ny;
   const size_t tiles = std::max(((nx + 31) / 32) * ((ny + 15) / 16), ((nx + 63) / 64) * ((ny + 7) / 8));
   if (c->tile_partials_cap >= 4 * tiles) return SGN_OK;
@@ -473,7 +481,7 @@ sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
   c->N = N;
   c->esize = p->dtype == SGN_F64 ? sizeof(double) : sizeof(float);
   c->tile_y = p->dtype == SGN_F64 ? 8 : 16;  // measured best on MI355X at 4096^2
-  c->step_tile = 16;
+  c->step_tile = 24;  // the step kernel's 32 x 24 tile: measured best on MI355X
   c->stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
@@ -627,8 +635,8 @@ sgn_status sgn_set_option(sgn_ctx* c, int32_t option, int64_t value) {
       return fail(c, SGN_E_ARG, "unknown step path");
     c->step_path = (int)value;
   } else if (option == SGN_OPT_TILE_Y) {
-    if (value != 8 && value != 16) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8 or 16");
-    c->tile_y = (int)value;
+    if (value != 8 && value != 16 && value != 24) return fail(c, SGN_E_UNSUPPORTED, "tile height must be 8, 16 or 24");
+    c->tile_y = value == 24 ? 16 : (int)value;
     c->step_tile = (int)value;
   } else if (option == SGN_OPT_ADJOINT_STORE) {
     if (value < 0) return fail(c, SGN_E_ARG, "adjoint storage must be >= 0 bytes");

@@ -525,9 +525,13 @@ __global__ __launch_bounds__(STAGE_THREADS) void vjp_kernel(const GridConst gc, 
 // the evaluations and read back (6 values each way, mostly served by L2); the
 // price is the ring of first evaluations (1 + 2 (TX + 2 + TY) / 512 of them
 // per owned node).
+// The reverse kernels use the 512-node step tiles: 32 x 16 or 64 x 8.
+template <int TX>
+using VjpGeom = StepGeom<TX == 64 ? 8 : 16>;
+
 template <typename T, int TX>
 struct VjpPairSmem {
-  T f[12][StepGeom<TX>::TY + 4][TX + 4];  // h u v w eta b 1/h | seeds of h u v w eta
+  T f[12][VjpGeom<TX>::TY + 4][TX + 4];  // h u v w eta b 1/h | seeds of h u v w eta
 };
 
 template <typename T, int BCX, int BCY, int PAIR, int TX>
@@ -539,7 +543,8 @@ __global__ __launch_bounds__(STAGE_THREADS, 2) void vjp_pair_kernel(const GridCo
                                                                  T* __restrict__ Bb, T aA, T cqA, T cyA, T cqB,
                                                                  T cyB) {
   static_assert(PAIR == 1 || PAIR == 2, "PAIR is 2 (S4 + S3) or 1 (S2 + S1)");
-  using G = StepGeom<TX>;
+  using G = VjpGeom<TX>;
+  static_assert(G::TX == TX, "32 x 16 or 64 x 8 tiles");
   constexpr int TY = G::TY;
   constexpr int H = 2;  // LDS position of tile node (0, 0)
   constexpr int RXA = TX + 2 * H, REGA = RXA * (TY + 2 * H);
@@ -596,7 +601,7 @@ __global__ __launch_bounds__(STAGE_THREADS, 2) void vjp_pair_kernel(const GridCo
   slot[0] = tid < G::RING1;
   pr[0] = 0;
   pc[0] = 0;
-  if (slot[0]) ring_node<TX>(tid, pr[0], pc[0]);
+  if (slot[0]) ring_node<TY>(tid, pr[0], pc[0]);
   pr[1] = ly0;
   pc[1] = lx;
   pr[2] = ly0 + 1;

@@ -40,7 +40,7 @@ def test_rhs_vjp_matches_oracle(shape, bcs):
 
 
 @pytest.mark.parametrize("path", ["fused", "stages"])
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (REF, PER), (PER, REF)])
 def test_step_vjp_matches_oracle(bcs, ty, path):
     """One RK4 step's VJP on a ragged 70 x 45 grid: on the fused path two
@@ -66,7 +66,7 @@ def test_step_vjp_matches_oracle(bcs, ty, path):
 
 
 @pytest.mark.parametrize("shape", [(4, 4), (5, 7), (33, 17)])
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (REF, PER), (PER, REF)])
 def test_two_stage_reverse_on_grids_smaller_than_a_tile(shape, bcs, ty):
     """The two-stage reverse kernels where one tile covers the grid (its ring
@@ -140,7 +140,7 @@ def test_gauge_loss_grad_many_and_repeated_gauges():
     assert series.shape == (9, 300) and np.array_equal(series[:, 150:170], np.repeat(series[:, :1], 20, axis=1))
 
 
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bc", [PER, REF])
 def test_gradient_same_on_pair_and_fused_paths(bc, ty):
     """The rollout and the segment recomputation run on the context's step path,
@@ -181,14 +181,15 @@ def test_two_stage_reverse_independent_of_tile_shape(bcs):
     bb0 = rng.standard_normal(b.shape)
     dt = 0.2 * oracle.cfl_dt(g, q, 0.5)
     outs = []
-    for ty in (8, 16):
+    for ty in (8, 16, 24):
         s = solver(g)
         s.set_tile_y(ty)
         s.set_bathymetry(dev(b))
         qb, bb = dev(a), dev(bb0)
         s.step_vjp(dev(q), dt, qb, bb)
         outs.append((host(qb), host(bb)))
-    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0][0], o[0]) and np.array_equal(outs[0][1], o[1])
 
 
 @pytest.mark.parametrize("path", ["fused", "pairs"])

@@ -51,11 +51,15 @@ def run_batch(probs, dtype, dts, nsteps, tiling=None, path=None):
 
 
 @pytest.mark.parametrize("path", ["fused", "pairs"])
-@pytest.mark.parametrize("dtype,ty", [(torch.float64, 8), (torch.float64, 16), (torch.float32, 16)])
+@pytest.mark.parametrize("dtype,ty", [(torch.float64, 8), (torch.float64, 16), (torch.float32, 16),
+                                      (torch.float64, 24), (torch.float32, 24)])
 @pytest.mark.parametrize("nsteps", [1, 2, 11])
 @pytest.mark.parametrize("bpc", [0, 2])
 def test_batch_equals_single_solver(path, dtype, ty, nsteps, bpc):
-    """bpc 0: one workgroup per tile; 2: a persistent grid."""
+    """bpc 0: one workgroup per tile; 2: a persistent grid (not for 32 x 24
+    step tiles, which run one workgroup per tile; 24 is a step-tile height)."""
+    if ty == 24 and (bpc != 0 or path != "fused"):
+        pytest.skip("32 x 24 tiles: fused path, one workgroup per tile")
     probs = small_ensemble()
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
     _, outs = run_batch(probs, dtype, dts, nsteps, (ty, bpc), path)
@@ -99,7 +103,7 @@ def test_batch_autotune_reads_states_only():
     batch.set_states(qs)
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
     ty, bpc, ms = batch.autotune(dts)
-    assert ty in (8, 16) and 0 <= bpc <= 6 and ms > 0
+    assert ty in (8, 16, 24) and 0 <= bpc <= 6 and ms > 0 and (ty != 24 or bpc == 0)
     for q, p in zip(qs, probs):
         assert np.array_equal(host(q), p[1])
     batch.step(dts, 2)

@@ -285,7 +285,7 @@ def test_step_paths_and_tiles(shape, bcs):
     ref3 = oracle.rk4(g, q, b, dt, 3)
     outs = []
     for path in PATHS:
-        for ty in (8, 16):
+        for ty in ((8, 16, 24) if path == "fused" else (8, 16)):
             s = solver(g)
             s.set_step_path(path)
             s.set_tile_y(ty)
@@ -300,12 +300,13 @@ def test_step_paths_and_tiles(shape, bcs):
         assert np.array_equal(o, outs[0]), k + 1
 
 
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bc", [PER, REF])
 def test_step_paths_mms_source(bc, ty):
     """Stage times reach the source correctly on every path (direct launches),
-    with both tile shapes of the step kernel (64 x 8 and 32 x 16) and of the
-    pair and stage kernels."""
+    with both tile shapes the step kernel runs source terms on (64 x 8 and
+    32 x 16; a 32 x 24 setting runs them on 32 x 16) and of the pair and stage
+    kernels."""
     g = W.mms_grid(40, bc)
     p = W.mms_initial(g)
     q0 = oracle.init_aux(g, p.q0, p.b)
@@ -347,7 +348,7 @@ def test_fused_path_long_run_matches_oracle(bcs):
     dt = oracle.cfl_dt(g, q, 0.5)
     for n in (20, 21):
         ref = oracle.rk4(g, q, b, dt, n)
-        for ty in (8, 16):
+        for ty in (8, 16, 24):
             s = solver(g)
             s.set_step_path("fused")
             s.set_tile_y(ty)
@@ -366,7 +367,7 @@ def test_fused_path_fp32_bounded_by_oracle_fp32():
     dt = oracle.cfl_dt(g, q0, 0.5)
     ref = oracle.rk4(g, q0, p.b, dt, 50)
     bound = field_rel_err(oracle.rk4_f32(g, q0, p.b, dt, 50).astype(np.float64), ref, STATE_FLOORS)
-    for ty in (8, 16):
+    for ty in (8, 16, 24):
         s = solver(g, torch.float32)
         s.set_step_path("fused")
         s.set_tile_y(ty)

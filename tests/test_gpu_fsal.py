@@ -80,7 +80,7 @@ def test_adaptive_run_matches_oracle(bc, path):
     assert np.all(err <= F64_TOL), err
 
 
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bc", [PER, REF])
 def test_fused_attempt_matches_role_kernels_bitwise(bc, ty):
     """The one-launch middle evaluations and the four role kernels do the same
@@ -133,7 +133,7 @@ def test_too_large_first_step_is_rejected_like_the_oracle(path):
 
 
 @pytest.mark.parametrize("path", PATHS)
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
 def test_fixed_steps_match_oracle(bcs, ty, path):
     """Fixed steps (adaptive = 0) on a ragged grid: the state after 7 steps and
@@ -151,7 +151,7 @@ def test_fixed_steps_match_oracle(bcs, ty, path):
 
 
 @pytest.mark.parametrize("shape", [(4, 4), (5, 7), (33, 17)])
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("bcs", [(PER, PER), (REF, REF), (PER, REF), (REF, PER)])
 def test_fused_attempt_on_grids_smaller_than_a_tile(shape, bcs, ty):
     """The attempt kernel where one tile covers the grid (rings and nodes past

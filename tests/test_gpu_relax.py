@@ -44,7 +44,7 @@ def test_relaxation_matches_oracle(bc, path):
     assert math.isclose(t_end, t_ref, rel_tol=1e-13), (t_end, t_ref)
 
 
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 def test_relaxation_step_kernel_tile_shapes(ty):
     """On the step kernel the first Newton iteration's sums come from the
     kernel's own tiles (4 doubles per tile): both tile shapes, grids with

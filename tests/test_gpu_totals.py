@@ -34,7 +34,7 @@ def problem(bc, nx, ny, seed):
 
 
 @pytest.mark.parametrize("bc", [PER, REF])
-@pytest.mark.parametrize("ty", [8, 16])
+@pytest.mark.parametrize("ty", [8, 16, 24])
 @pytest.mark.parametrize("n", [1, 8, 13])
 def test_series_matches_per_step_totals(bc, ty, n):
     g, q0, b = problem(bc, 77, 45, seed=n + ty)

@@ -3,7 +3,7 @@
 A model of the kernel's index arithmetic, phase by phase as its barriers
 separate them: staging (every thread writes its share of the region),
 then for each of the four stages an evaluation phase (LDS reads only: the
-owned pair of nodes per thread, then up to two ring nodes) and a write-back
+two or three owned nodes per thread, then up to two ring nodes) and a write-back
 phase (the stage just formed replaces the one read).  For every tile of a
 grid the replay checks that
 
@@ -14,8 +14,9 @@ grid the replay checks that
     state for k1, Y_s for k_s), written in an earlier phase; the bathymetry
     plane is written once, at staging;
   * no slot is written twice in one write-back phase;
-  * the paired node shares its centre and lower neighbour with node 0's upper
-    neighbour and centre exactly when the kernel relies on it;
+  * node 1 shares its centre and lower neighbour with node 0's upper
+    neighbour and centre, and node 2 its lower neighbour with node 1's centre,
+    exactly when the kernel relies on it;
   * ring slots 0 .. RING3-1 cover the rings at distance 1..3 once each.
 
 The replay covers the manufactured-source instances too: the source is added
@@ -28,8 +29,8 @@ import pytest
 
 PER, REF = 0, 1
 THREADS = 256
-NODES = 512
 HALO = 4
+SHAPES = {8: 64, 16: 32, 24: 32}  # tile height -> width: 64 x 8, 32 x 16, 32 x 24
 PLANES = 7          # h u v w eta b 1/h
 B_PLANE = 5
 
@@ -96,8 +97,9 @@ class Lds:
             assert got == (0 if f == B_PLANE else want), ("stale stage", f, r, c, got, want)
 
 
-def replay_tile(nx, ny, bcx, bcy, tx, pad, i0, j0, skip_slot=None):
-    ty = NODES // tx
+def replay_tile(nx, ny, bcx, bcy, ty, pad, i0, j0, skip_slot=None):
+    tx = SHAPES[ty]
+    no = tx * ty // THREADS  # owned nodes per thread
     rx, ry = tx + 2 * HALO, ty + 2 * HALO
     rings = [ring_count(tx, ty, 1)]
     rings += [rings[0] + ring_count(tx, ty, 2), rings[0] + ring_count(tx, ty, 2) + ring_count(tx, ty, 3)]
@@ -115,9 +117,9 @@ def replay_tile(nx, ny, bcx, bcy, tx, pad, i0, j0, skip_slot=None):
     # thread map
     own = []
     for tid in range(THREADS):
-        lx, ly0 = tid % tx, 2 * (tid // tx)
+        lx, ly0 = tid % tx, no * (tid // tx)
         i, j = i0 + lx, j0 + ly0
-        own.append((lx, ly0, i, j, [on_axis(i, nx, bcx) and on_axis(j + k, ny, bcy) for k in (0, 1)]))
+        own.append((lx, ly0, i, j, [on_axis(i, nx, bcx) and on_axis(j + k, ny, bcy) for k in range(no)]))
     ring = []
     for tid in range(THREADS):
         for k in (0, 1):
@@ -131,24 +133,31 @@ def replay_tile(nx, ny, bcx, bcy, tx, pad, i0, j0, skip_slot=None):
         ring_lim = rings[3 - st] if st < 4 else 0
         # evaluation phase: reads only
         for lx, ly0, i, j, od in own:
-            run0 = od[0] if st < 4 else (i < nx and j < ny)
-            run1 = od[1] if st < 4 else (i < nx and j + 1 < ny)
-            if not run0:
+            run = [od[k] if st < 4 else (i < nx and j + k < ny) for k in range(no)]
+            if not run[0]:
                 continue
             r, c = ly0 + HALO, lx + HALO
             om, op = stencil(i, nx, bcx)
             ym0, yp0 = stencil(j, ny, bcy)
             for rr, cc in ((r, c), (r + yp0, c), (r, c + om), (r, c + op), (r + ym0, c)):
                 lds.read_node(rr, cc, want)
-            if run1:
+            if run[1]:
                 ym1, yp1 = stencil(j + 1, ny, bcy)
                 # node 1's centre is node 0's upper neighbour, its lower neighbour node 0's centre
                 assert r + yp0 == r + 1 and (r + 1) + ym1 == r, (i, j)
                 for rr, cc in ((r + 1, c + om), (r + 1, c + op), (r + 1 + yp1, c)):
                     lds.read_node(rr, cc, want)
+                if no == 3 and run[2]:
+                    ym2, yp2 = stencil(j + 2, ny, bcy)
+                    # node 2's lower neighbour is node 1's centre; its own centre is read again
+                    assert (r + 2) + ym2 == r + 1, (i, j)
+                    for rr, cc in ((r + 2, c), (r + 2, c + om), (r + 2, c + op), (r + 2 + yp2, c)):
+                        lds.read_node(rr, cc, want)
+            elif no == 3:
+                assert not run[2], (i, j)  # node 2 in the domain implies node 1 in the domain
             if st == 4:
-                for k in (0, 1):
-                    if (run0, run1)[k]:
+                for k in range(no):
+                    if run[k]:
                         lds.slot(B_PLANE, ly0 + k + HALO, lx + HALO)  # epilogues read b of the owned node
         if st == 4:
             break
@@ -163,7 +172,7 @@ def replay_tile(nx, ny, bcx, bcy, tx, pad, i0, j0, skip_slot=None):
         # write-back phase: the stage just formed (every plane but b)
         seen = set()
         for lx, ly0, i, j, od in own:
-            for k in (0, 1):
+            for k in range(no):
                 if od[k]:
                     for f in range(PLANES):
                         if f != B_PLANE:
@@ -175,16 +184,16 @@ def replay_tile(nx, ny, bcx, bcy, tx, pad, i0, j0, skip_slot=None):
                         lds.write(f, rr + HALO, cc + HALO, st, seen)
 
 
-def tiles(nx, ny, tx):
-    ty = NODES // tx
+def tiles(nx, ny, ty):
+    tx = SHAPES[ty]
     for j0 in range(0, ny, ty):
         for i0 in range(0, nx, tx):
             yield i0, j0
 
 
-@pytest.mark.parametrize("tx", [32, 64])
-def test_ring_map_covers_each_ring_node_once(tx):
-    ty = NODES // tx
+@pytest.mark.parametrize("ty", [8, 16, 24])
+def test_ring_map_covers_each_ring_node_once(ty):
+    tx = SHAPES[ty]
     total = sum(ring_count(tx, ty, d) for d in (1, 2, 3))
     got = [ring_node(m, tx, ty) for m in range(total)]
     assert len(set(got)) == total
@@ -193,27 +202,27 @@ def test_ring_map_covers_each_ring_node_once(tx):
     assert set(got) == expect
 
 
-@pytest.mark.parametrize("tx,pad", list(itertools.product([32, 64], [0, 1])))
+@pytest.mark.parametrize("ty,pad", list(itertools.product([8, 16, 24], [0, 1])))
 @pytest.mark.parametrize("bcx,bcy", [(REF, REF), (PER, PER), (REF, PER), (PER, REF)])
-def test_schedule_40x40(tx, pad, bcx, bcy):
+def test_schedule_40x40(ty, pad, bcx, bcy):
     """The grid of the manufactured-solution tests (40 x 40): every tile."""
-    for i0, j0 in tiles(40, 40, tx):
-        replay_tile(40, 40, bcx, bcy, tx, pad, i0, j0)
+    for i0, j0 in tiles(40, 40, ty):
+        replay_tile(40, 40, bcx, bcy, ty, pad, i0, j0)
 
 
-@pytest.mark.parametrize("tx", [32, 64])
-@pytest.mark.parametrize("nx,ny", [(4, 4), (5, 9), (70, 257), (129, 33)])
-def test_schedule_ragged_and_tiny(tx, nx, ny):
+@pytest.mark.parametrize("ty", [8, 16, 24])
+@pytest.mark.parametrize("nx,ny", [(4, 4), (5, 9), (70, 257), (129, 33), (33, 25), (40, 49)])
+def test_schedule_ragged_and_tiny(ty, nx, ny):
     for bcx, bcy in ((REF, REF), (PER, PER)):
-        for i0, j0 in tiles(nx, ny, tx):
-            replay_tile(nx, ny, bcx, bcy, tx, 1, i0, j0)
+        for i0, j0 in tiles(nx, ny, ty):
+            replay_tile(nx, ny, bcx, bcy, ty, 1, i0, j0)
 
 
 def test_replay_detects_a_stale_neighbour():
     """The replay is sharp: leaving out one ring-3 node at stage 1 leaves a stale
     value that a ring-2 evaluation reads at stage 2."""
-    tx, ty = 64, NODES // 64
+    ty, tx = 8, SHAPES[8]
     last = ring_count(tx, ty, 1) + ring_count(tx, ty, 2) + ring_count(tx, ty, 3) - 1
-    replay_tile(200, 200, PER, PER, tx, 1, 64, 64)
+    replay_tile(200, 200, PER, PER, ty, 1, 64, 64)
     with pytest.raises(AssertionError, match="stale stage"):
-        replay_tile(200, 200, PER, PER, tx, 1, 64, 64, skip_slot=last)
+        replay_tile(200, 200, PER, PER, ty, 1, 64, 64, skip_slot=last)
