@@ -68,17 +68,15 @@ SETTLE_STEPS = 64
 # steps (beside its run that recomputes every step).
 ADJOINT_STORE_CAP_BYTES = 240 * 2**30
 # HBM traffic of the step kernel on the default workload (4096^2 periodic FP64,
-# 32 x 16 tiles), from the FETCH_SIZE and WRITE_SIZE passes summarized in
-# profiles/step_kernel_random_phase_4096_periodic_f64.md (FETCH_SIZE scaled by
-# 2.0 and WRITE_SIZE by 1.0, the factors a plain 1 GiB copy reads): bytes per
-# node and launch.  Reported only while the kernel sources hash to the value
-# they had when the counters were taken (or to a later version whose step
-# kernel assembles to the same instructions: the source-term function made a
-# real call changed only the source-term instantiations).
-STEP_TRAFFIC_BYTES_PER_NODE = (1190166094.0 + 671088640.0) / 16777216
+# its default 32 x 24 tiles), from the FETCH_SIZE and WRITE_SIZE passes
+# summarized in profiles/step_kernel_random_phase_4096_periodic_f64.md
+# (FETCH_SIZE scaled by 1.99992 and WRITE_SIZE by 1.0, the factors a plain
+# 1 GiB copy reads): bytes per node and launch.  Reported only while the kernel
+# sources hash to the value they had when the counters were taken.
+STEP_TRAFFIC_BYTES_PER_NODE = (1082889614.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "2abd4d87e30e9a46065277f6e3f5e819be2240b0d2503b0ac6ba56b1067125c2"
+STEP_SOURCES_SHA256 = "6db076ebd6e5c8a34081a0f889d2c3b0d267b07bd3df93062c4c6b506d6a0c5c"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}
@@ -781,7 +779,7 @@ def roofline(path, res, cells, esize=8):
     reported beside it."""
     values, launches = PATHS[path]
     traffic = None
-    if path == "fused" and esize == 8 and cells == 4096 * 4096 and res["tile_y"] in (None, 16) and \
+    if path == "fused" and esize == 8 and cells == 4096 * 4096 and res["tile_y"] in (None, 24) and \
             step_sources_unchanged():
         traffic = STEP_TRAFFIC_BYTES_PER_NODE * cells
     out = dict(bound="hbm", achieved=res["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=res["frac"],
@@ -816,8 +814,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true", help="skip the reflecting and FP32 repeats")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=sorted(PATHS), default="fused", help="step path of the main run")
-    ap.add_argument("--tile-y", type=int, choices=(8, 16), default=None,
-                    help="tile height (default: the library's per-dtype default)")
+    ap.add_argument("--tile-y", type=int, choices=(8, 16, 24), default=None,
+                    help="tile height (default: the library's defaults; 24 = 32 x 24 step tiles)")
     ap.add_argument("--variants", default="all",
                     help="comma list of extra runs: f32,reflecting,ensemble,small,adjoint,paths,paper,relaxation,"
                          "totals,adaptive,longdrift (default all)")
