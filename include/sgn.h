@@ -101,7 +101,8 @@ typedef struct sgn_ctx sgn_ctx;
  * SGN_OPT_TILE_Y: 8, 16 or 24.  Tile height of the stage and pair kernels (64
  *   wide; default 8 for SGN_F64, 16 for SGN_F32) and of the step kernel's tile
  *   (8 selects 64 x 8, 16 selects 32 x 16, 24 selects 32 x 24: three owned
- *   nodes per thread and the fewest redundant ring evaluations; default 24).
+ *   nodes per thread and the fewest redundant ring evaluations; default 24
+ *   when the grid holds at least 1024 tiles of 32 x 24, 16 otherwise).
  *   8 and 16 set both; 24 sets the step tile and height 16 for the stage and
  *   pair kernels.  With a 32 x 24 step tile, steps that save stage states or
  *   add source terms, and the adaptive pair's attempt kernel, run 32 x 16

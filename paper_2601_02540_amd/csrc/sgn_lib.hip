@@ -481,7 +481,9 @@ sgn_status sgn_create(const sgn_params* p, void* stream, sgn_ctx** out) {
   c->N = N;
   c->esize = p->dtype == SGN_F64 ? sizeof(double) : sizeof(float);
   c->tile_y = p->dtype == SGN_F64 ? 8 : 16;  // measured best on MI355X at 4096^2
-  c->step_tile = 24;  // the step kernel's 32 x 24 tile: measured best on MI355X
+  // the step kernel's 32 x 24 tile (measured best on MI355X) once the grid has
+  // enough of them to fill the GPU (four workgroups per CU); 32 x 16 below that
+  c->step_tile = ((p->nx + 31) / 32) * ((p->ny + 23) / 24) >= 1024 ? 24 : 16;
   c->stream = (hipStream_t)stream;
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) {
