@@ -72,11 +72,13 @@ ADJOINT_STORE_CAP_BYTES = 240 * 2**30
 # summarized in profiles/step_kernel_random_phase_4096_periodic_f64.md
 # (FETCH_SIZE scaled by 1.99992 and WRITE_SIZE by 1.0, the factors a plain
 # 1 GiB copy reads): bytes per node and launch.  Reported only while the kernel
-# sources hash to the value they had when the counters were taken.
+# sources hash to the value they had when the counters were taken (or to a later
+# version whose step kernel assembles to the same instructions: the relaxed-input
+# mode of the step tile added other instantiations only).
 STEP_TRAFFIC_BYTES_PER_NODE = (1082889614.0 + 671088640.0) / 16777216
 STEP_KERNEL_SOURCES = ("sgn_common.hpp", "sgn_stage.hpp", "sgn_mms.hpp", "sgn_pair.hpp", "sgn_reduce.hpp",
                        "sgn_fused.hpp")
-STEP_SOURCES_SHA256 = "6db076ebd6e5c8a34081a0f889d2c3b0d267b07bd3df93062c4c6b506d6a0c5c"
+STEP_SOURCES_SHA256 = "4e8c6d844ce4d6910838e883f1ad1701f29b44e44029454f19aa51055cbf82fb"
 KERNELS = {"pairs": "pair_kernel (two fused RK4 stages; mean over the 2 launches of a step)",
            "stages": "stage_kernel (fused RHS + RK4 stage; mean over the 4 launches of a step)",
            "fused": "step_kernel (one whole RK4 step per launch)"}

@@ -85,7 +85,19 @@ __device__ __forceinline__ Node<T> opaque_node(Node<T> n) {
 // tile first stages y, from which the owned and ring nodes keep their y in
 // registers (as the classical step keeps q), then overwrites it with Y_2; k_1
 // of the owned nodes is read again from global memory (L2).
-enum : int { RK_CLASSIC = 0, RK_FSAL = 1 };
+// RK_RELAXED: one classical RK4 step from the relaxed state of the previous
+// relaxation step, q = qa + gam (ra - qa), formed while staging (the arithmetic
+// of relax_update, so the same bits), which the tile also writes out for its
+// owned nodes (RelaxIn).
+enum : int { RK_CLASSIC = 0, RK_FSAL = 1, RK_RELAXED = 2 };
+
+// Operands of an RK_RELAXED tile: q (the step's input pointer) is qa.
+template <typename T>
+struct RelaxIn {
+  const T* ra;             // the previous step's RK4 result
+  const double* rs;        // rs[0] = gam of the previous step
+  T* qbase;                // out: the relaxed state of the owned nodes
+};
 
 // Coefficients and extra operands of an RK_FSAL tile (h already applied).
 template <typename T>
@@ -149,8 +161,10 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
                                           T* __restrict__ qout, T c6, T c3, T c2, T c1, double t0, double dt,
                                           int* __restrict__ flag, T* __restrict__ ysave,
                                           double* __restrict__ rpart = nullptr,
-                                          const FsalStage<T>* __restrict__ fx = nullptr) {
-  static_assert(RK == RK_CLASSIC || (!SRC && !SAVE && EPI == EPI_NONE), "the FSAL tile has no extras");
+                                          const FsalStage<T>* __restrict__ fx = nullptr,
+                                          const RelaxIn<T>* __restrict__ rx = nullptr) {
+  static_assert(RK != RK_FSAL || (!SRC && !SAVE && EPI == EPI_NONE), "the FSAL tile has no extras");
+  static_assert(RK != RK_RELAXED || (!SRC && !SAVE), "the relaxed tile has no source or stage saving");
   using G = StepGeom<TY>;
   constexpr int TX = G::TX, NO = G::NO;
   constexpr int RX = G::RX;
@@ -169,7 +183,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
   {
     constexpr int ITER = (REGION + STAGE_THREADS - 1) / STAGE_THREADS;
     T v[ITER][6];
-    T kst[RK == RK_FSAL ? ITER : 1][5];
+    T kst[RK != RK_CLASSIC ? ITER : 1][5];
     // The staging waves take the issue priority until the barrier: their loads
     // and LDS writes go out ahead of the other workgroup's evaluation on the
     // same SIMDs (measured: FP32 2% and FP64 0.3-0.5% faster, same bits).
@@ -190,6 +204,10 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
 #pragma unroll
           for (int f = 0; f < 5; ++f) kst[it][f] = fx->k1[f * N + o];
         }
+        if constexpr (RK == RK_RELAXED) {
+#pragma unroll
+          for (int f = 0; f < 5; ++f) kst[it][f] = rx->ra[f * N + o];
+        }
       }
     }
 #pragma unroll
@@ -198,9 +216,14 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
       if (idx < REGION) {
         const int rr = idx / RX;
         const int cc = idx - rr * RX;
+        if constexpr (RK == RK_RELAXED) {
+          const T gam = T(rx->rs[0]);
+#pragma unroll
+          for (int f = 0; f < 5; ++f) v[it][f] = v[it][f] + gam * (kst[it][f] - v[it][f]);
+        }
 #pragma unroll
         for (int f = 0; f < 6; ++f) s.f[f][rr][cc] = v[it][f];
-        if constexpr (RK == RK_CLASSIC) s.f[6][rr][cc] = recip_staged(v[it][0]);
+        if constexpr (RK != RK_FSAL) s.f[6][rr][cc] = recip_staged(v[it][0]);
       }
     }
     if constexpr (RK == RK_FSAL) {
@@ -337,6 +360,13 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
           acc[k][f] = yv[f] + ca * kv[f];
           ro[k][f] = yv[f] + cy * kv[f];
         }
+        if constexpr (RK == RK_RELAXED) {
+          if (i < nx && j < ny) {
+            const size_t o = (size_t)j * nx + i;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) rx->qbase[f * N + o] = yv[f];
+          }
+        }
       } else if (st < 4) {
 #pragma unroll
         for (int f = 0; f < 5; ++f) {
@@ -446,7 +476,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
       const Rates<T> kk = tile_eval<T, BCX, BCY, SRC>(s, ring_r[k] + STEP_HALO, ring_c[k] + STEP_HALO,
                                                       i0 + ring_c[k], j0 + ring_r[k], gc, ts, cn);
       const T kv[5] = {kk.h, kk.u, kk.v, kk.w, kk.eta};
-      if constexpr (RK == RK_CLASSIC) {
+      if constexpr (RK != RK_FSAL) {
         if (st == 1) {
           qr[k][0] = cn.h;
           qr[k][1] = cn.u;
@@ -479,7 +509,7 @@ __device__ __forceinline__ void step_tile(StepSmem<T, TY, PAD>& s, const GridCon
     }
     __syncthreads();
   }
-  if constexpr (RK == RK_CLASSIC) {
+  if constexpr (RK != RK_FSAL) {
     if (health) atomicOr(flag, health);
   }
   if (EPI != EPI_NONE) {

@@ -22,6 +22,7 @@
 // storage type, with compensated, deterministic reductions.
 #pragma once
 
+#include "sgn_fused.hpp"
 #include "sgn_reduce.hpp"
 
 namespace sgn {
@@ -112,15 +113,37 @@ static __global__ void relax_set_time(double* __restrict__ rs, double t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) rs[1] = t0;
 }
 
-// q <- q + gam (q_RK4 - q), elementwise over the five planes.
+// out <- q + gam (q_RK4 - q), elementwise over the five planes (out may be q).
 template <typename T>
-__global__ __launch_bounds__(256) void relax_update(size_t n5, T* __restrict__ q, const T* __restrict__ qrk,
+__global__ __launch_bounds__(256) void relax_update(size_t n5, T* out, const T* q, const T* __restrict__ qrk,
                                                     const double* __restrict__ rs) {
   const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (k >= n5) return;
   const T gam = T(rs[0]);
   const T x = q[k];
-  q[k] = x + gam * (qrk[k] - x);
+  out[k] = x + gam * (qrk[k] - x);
+}
+
+// One RK4 step of a relaxation run after its first: the step tile stages the
+// relaxed state of the previous step, qa + gam (ra - qa), writes it out for
+// its owned nodes (qbase) beside the RK4 result (qout), and reduces the first
+// Newton iteration's sums per tile (EPI_RELAX), so no update pass runs between
+// the steps.
+template <typename T, int BCX, int BCY, int TY>
+__global__ __launch_bounds__(STAGE_THREADS) void relax_step_kernel(const GridConst gc, const T* __restrict__ qa,
+                                                                   const T* __restrict__ bplane,
+                                                                   T* __restrict__ qout, const RelaxIn<T> rx, T c6,
+                                                                   T c3, T c2, T c1, double dt,
+                                                                   int* __restrict__ flag,
+                                                                   double* __restrict__ rpart) {
+  constexpr int TX = StepGeom<TY>::TX;
+  __shared__ StepSmem<T, TY, 1> s;
+  const int ntx = (gc.nx + TX - 1) / TX;
+  const int nty = (gc.ny + TY - 1) / TY;
+  const int tile = xcd_tile(blockIdx.x, ntx * nty);
+  step_tile<T, BCX, BCY, false, TY, false, 1, EPI_RELAX, RK_RELAXED>(
+      s, gc, (tile % ntx) * TX, (tile / ntx) * TY, qa, bplane, qout, c6, c3, c2, c1, 0.0, dt, flag, nullptr,
+      rpart + 4 * tile, nullptr, &rx);
 }
 
 }  // namespace sgn

@@ -63,6 +63,33 @@ def test_relaxation_step_kernel_tile_shapes(ty):
         assert math.isclose(t_end, t_ref, rel_tol=1e-13), (t_end, t_ref)
 
 
+@pytest.mark.parametrize("ty", [16, 24])
+@pytest.mark.parametrize("bc", [PER, REF])
+def test_relaxation_step_counts_with_staged_updates(bc, ty):
+    """On the step-kernel paths every step after the first of a call (or of a
+    graph replay of 8) stages the previous step's relaxed state itself and the
+    update pass runs once at the end, from one of two buffer pairs: step counts
+    that end on either pair, inside and across graph replays, one call after
+    another, against the oracle."""
+    g, q0, b = wavy(bc, 70, 53, seed=3)
+    dt = oracle.cfl_dt(g, q0, 0.25)  # 40 steps in all: the wavy state stays wet
+    s = solver(g)
+    s.set_tile_y(ty)
+    s.set_bathymetry(dev(b))
+    qd = dev(q0)
+    q_ref, t_prev = q0, 0.0
+    for n in (1, 2, 3, 8, 9, 17):
+        q_ref, t_ref, _ = oracle.rk4_relax(g, q_ref, b, dt, n, t_prev)
+        t_end = s.step_relaxation(qd, dt, n, t_prev)
+        err = field_rel_err(host(qd), q_ref, STATE_FLOORS)
+        assert np.all(err <= 1e-12), (n, err)
+        # at this quarter-CFL step the energy change per step is small, so gam
+        # carries the summation-order rounding of the energy sums (GPU tile and
+        # block order against the oracle's row order) to ~3e-13 relative
+        assert math.isclose(t_end, t_ref, rel_tol=1e-12), (n, t_end, t_ref)
+        t_prev = t_ref
+
+
 def test_relaxation_single_step_parameter():
     g, q0, b = wavy(PER, 64, 64, seed=3)
     dt = oracle.cfl_dt(g, q0, 0.5)
