@@ -105,8 +105,8 @@ typedef struct sgn_ctx sgn_ctx;
  *   when the grid holds at least 1024 tiles of 32 x 24, 16 otherwise).
  *   8 and 16 set both; 24 sets the step tile and height 16 for the stage and
  *   pair kernels.  With a 32 x 24 step tile, steps that save stage states or
- *   add source terms, and the adaptive pair's attempt kernel, run 32 x 16
- *   tiles.  Every tile shape forms the same values.
+ *   add source terms, and the adaptive pair's attempt kernel on grids with a
+ *   wall, run 32 x 16 tiles.  Every tile shape forms the same values.
  * SGN_OPT_ADJOINT_STORE: bytes of device memory (>= 0; default 0) that
  *   sgn_gauge_loss_grad may fill with the states and stage states of the last
  *   steps of its forward rollout, so that its reverse sweep need not recompute

@@ -79,9 +79,10 @@ hipError_t enqueue_attempt_ty(const sgn_ctx* c, hipStream_t s, void* q, double* 
     else hipLaunchKernelGGL((sgn::fsal_kernel<T, 1, 1, R, TY>), grid, block, 0, s, c->gc, a);                \
   } while (0)
   if (c->step_path == SGN_PATH_FUSED) {
-    // S2 .. S5 in one launch of the step tile (32 x 16 where the context's step
-    // tile is 32 x 24: the attempt's 32 x 24 instances reach the register limit)
-    const int ty = c->step_tile == 8 ? 8 : 16;
+    // S2 .. S5 in one launch of the step tile; with the context's 32 x 24 step
+    // tile, 32 x 24 on periodic grids and 32 x 16 otherwise (the attempt's
+    // 32 x 24 instances with a wall reach the register limit)
+    const int ty = c->step_tile == 8 ? 8 : (c->step_tile == 24 && bx == 0 && by == 0 ? 24 : 16);
     const int tx = ty == 8 ? sgn::StepGeom<8>::TX : sgn::StepGeom<16>::TX;
     const int sx = (c->p.nx + tx - 1) / tx, sy = (c->p.ny + ty - 1) / ty;
     const dim3 sgrid((unsigned)(sx * sy));
@@ -92,7 +93,8 @@ hipError_t enqueue_attempt_ty(const sgn_ctx* c, hipStream_t s, void* q, double* 
     else if (bx == 1 && by == 0) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 0, TY_>), sgrid, block, 0, s, c->gc, a); \
     else hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 1, 1, TY_>), sgrid, block, 0, s, c->gc, a);                   \
   } while (0)
-    if (ty == 16) SGN_FSTEP(16);
+    if (ty == 24) hipLaunchKernelGGL((sgn::fsal_step_kernel<T, 0, 0, 24>), sgrid, block, 0, s, c->gc, a);
+    else if (ty == 16) SGN_FSTEP(16);
     else SGN_FSTEP(8);
 #undef SGN_FSTEP
   } else {
