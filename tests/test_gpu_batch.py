@@ -50,16 +50,18 @@ def run_batch(probs, dtype, dts, nsteps, tiling=None, path=None):
     return batch, [host(q) for q in qs]
 
 
-@pytest.mark.parametrize("path", ["fused", "pairs"])
-@pytest.mark.parametrize("dtype,ty", [(torch.float64, 8), (torch.float64, 16), (torch.float32, 16),
-                                      (torch.float64, 24), (torch.float32, 24)])
+# (path, dtype, tile height, blocks per CU): 32 x 24 step tiles exist on the
+# fused path only and run one workgroup per tile
+BATCH_CASES = [(path, dtype, ty, bpc) for path in ("fused", "pairs")
+               for dtype, ty in ((torch.float64, 8), (torch.float64, 16), (torch.float32, 16), (torch.float64, 24),
+                                 (torch.float32, 24))
+               for bpc in (0, 2) if ty != 24 or (path == "fused" and bpc == 0)]
+
+
+@pytest.mark.parametrize("path,dtype,ty,bpc", BATCH_CASES)
 @pytest.mark.parametrize("nsteps", [1, 2, 11])
-@pytest.mark.parametrize("bpc", [0, 2])
-def test_batch_equals_single_solver(path, dtype, ty, nsteps, bpc):
-    """bpc 0: one workgroup per tile; 2: a persistent grid (not for 32 x 24
-    step tiles, which run one workgroup per tile; 24 is a step-tile height)."""
-    if ty == 24 and (bpc != 0 or path != "fused"):
-        pytest.skip("32 x 24 tiles: fused path, one workgroup per tile")
+def test_batch_equals_single_solver(path, dtype, ty, bpc, nsteps):
+    """bpc 0: one workgroup per tile; 2: a persistent grid."""
     probs = small_ensemble()
     dts = [0.2 * oracle.cfl_dt(g, q, 0.5) for g, q, b in probs]
     _, outs = run_batch(probs, dtype, dts, nsteps, (ty, bpc), path)
